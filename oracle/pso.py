@@ -24,9 +24,9 @@ defers the dynamical equations to earlier work.  The reading taken here:
     stream) with stream 0 = initial x, 1 = initial u, 2 = r1, 3 = r2; the four
     32-bit outputs feed the four coordinates as (w + 0.5) / 2^32.
 
-All arithmetic is IEEE float64 in a fixed order (no fused multiply-add), and
-fitness values are compared as float32, so that an implementation following
-the same order reproduces the trajectories bit for bit.
+All arithmetic is IEEE float64 in a fixed order (no fused multiply-add), so
+that an implementation following the same order reproduces the trajectories
+bit for bit given the same fitness values.
 """
 from __future__ import annotations
 
@@ -87,10 +87,10 @@ class PsoState:
     x: np.ndarray           # (R, P, 4) float64
     v: np.ndarray           # (R, P, 4) float64
     pbest_x: np.ndarray     # (R, P, 4) float64
-    pbest_f: np.ndarray     # (R, P) float32
+    pbest_f: np.ndarray     # (R, P) float64
     pbest_j: np.ndarray     # (R, P) int32
     best_x: np.ndarray = field(default=None)   # (R, 4)
-    best_f: np.ndarray = field(default=None)   # (R,) float32
+    best_f: np.ndarray = field(default=None)   # (R,) float64
     best_j: np.ndarray = field(default=None)   # (R,) int32
 
 
@@ -110,9 +110,9 @@ def init(p: PsoParams, lo, hi):
             u = uniforms4(p.seed, 0, i, r, 1)
             v[r, i] = np.minimum(np.maximum(u - x[r, i], -p.vmax), p.vmax)
     st = PsoState(x=x, v=v, pbest_x=x.copy(),
-                  pbest_f=np.full((R, P), -np.inf, dtype=np.float32),
+                  pbest_f=np.full((R, P), -np.inf),
                   pbest_j=np.full((R, P), -1, dtype=np.int32),
-                  best_x=np.zeros((R, 4)), best_f=np.full(R, -np.inf, dtype=np.float32),
+                  best_x=np.zeros((R, 4)), best_f=np.full(R, -np.inf),
                   best_j=np.full(R, -1, dtype=np.int32))
     return st, to_theta(x, lo, hi).reshape(R * P, 4)
 
@@ -127,7 +127,7 @@ def step(p: PsoParams, st: PsoState, fit, argmax, iteration: int, lo, hi):
     """One iteration given the fitness of the current positions; returns the
     parameters at which the next fitness batch is evaluated."""
     R, P = p.n_runs, p.n_particles
-    fit = np.asarray(fit, dtype=np.float32).reshape(R, P)
+    fit = np.asarray(fit, dtype=np.float64).reshape(R, P)
     argmax = np.asarray(argmax, dtype=np.int32).reshape(R, P)
     for r in range(R):
         for i in range(P):

@@ -1,0 +1,42 @@
+// eval_f64.hip -- double instantiation of the FFT passes and the finalize kernel.
+#include "launch.hpp"
+
+namespace fcas {
+
+#define FCAS_CASE_P1(id, ...)                                                              \
+  case id:                                                                                  \
+    hipLaunchKernelGGL((k_pass1<double, PlanD##id>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); \
+    break;
+#define FCAS_CASE_P2(id, ...)                                                              \
+  case id:                                                                                  \
+    hipLaunchKernelGGL((k_pass2<double, PlanD##id>), dim3(grid), dim3(PlanD##id::T2), 0, s, a); \
+    break;
+
+hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
+  switch (plan) {
+    FCAS_PLAN_LIST(FCAS_CASE_P1)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
+  switch (plan) {
+    FCAS_PLAN_LIST(FCAS_CASE_P2)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_f64(const EvalDesc* evals, const SegDesc* segs, const void* part_g,
+                                  const int32_t* part_j, int n, const int32_t* plan_tiles2, double* fitness,
+                                  int32_t* argmax, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize<double>, dim3((n + 127) / 128), dim3(128), 0, s, evals, segs,
+                     (const double*)part_g, part_j, n, plan_tiles2, fitness, argmax);
+  return hipGetLastError();
+}
+
+}  // namespace fcas

@@ -1,0 +1,169 @@
+// eval_kernels.hpp -- gfx950 kernels of fitness_eval_batch (included by the
+// per-precision translation units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fitness_tiles.hpp"
+#include "plans.hpp"
+
+namespace fcas {
+
+struct PassArgs {
+  const SegDesc* segs;
+  const EvalDesc* evals;
+  const int32_t* list;     // evaluation indices of this plan, in list order
+  const int32_t* count;    // number of entries in `list`
+  void* ws;                // workspace: cap slots of 2 N complex
+  void* part_g;            // [max_batch][kMaxTiles2] partial maxima (Real)
+  int32_t* part_j;         // [max_batch][kMaxTiles2] their samples
+  int32_t n_det;
+  int32_t chunk_begin;     // first list position handled by this launch
+  int32_t cap;             // workspace slots
+};
+
+// ---------------------------------------------------------------------------
+// Pass 1: prologue (template phase, delays, projection) + length-N1 column
+// FFTs + four-step twiddle, for C columns of one evaluation per work item.
+// ---------------------------------------------------------------------------
+template <typename Real, class PL, int L, int E, class Rad, int I, int Ns>
+__device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf, const cplx<Real>* tw, int t) {
+  if constexpr (I < Rad::count) {
+    constexpr int R = Rad::value[I];
+    constexpr bool LAST = (I == Rad::count - 1);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      stage_butterflies<Real, L, E, R, Ns, LAST>(v[s], buf, tw, t);
+      if constexpr (!LAST) {
+        __syncthreads();
+        stage_gather<Real, L, E>(v[s], buf, t);
+        __syncthreads();
+      }
+    }
+    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R>(v, buf, tw, t);
+  }
+}
+
+template <typename Real, class PL>
+__global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
+  constexpr int LP = lds_padded_len(PL::N1);
+  __shared__ cplx<Real> lds[PL::C * LP];
+  __shared__ cplx<Real> tw[PL::N1];
+  const int tid = threadIdx.x;
+  for (int m = tid; m < PL::N1; m += PL::T1) tw[m] = twiddle<Real>(m, PL::N1);
+  __syncthreads();
+  int cnt = *a.count - a.chunk_begin;
+  cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
+  const int items = cnt * PL::TILES1;
+  const int c = tid % PL::C, p = tid / PL::C;
+  cplx<Real>* buf = lds + c * LP;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int slot = item / PL::TILES1;
+    const int tile = item - slot * PL::TILES1;
+    const int e = a.list[a.chunk_begin + slot];
+    const EvalDesc& ev = a.evals[e];
+    const SegDesc& sg = a.segs[ev.seg];
+    cplx<Real> v[2][PL::E1];
+    pass1_prologue<Real, PL>(v, ev, sg, a.n_det, tile, c, p);
+    run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1>(v, buf, tw, p);
+    cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
+    pass1_store<Real, PL>(v, ws, tile, c, p);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Pass 2: length-N2 row FFTs, |a_0|^2 + |a_1|^2 and its maximum over the RW
+// rows of one work item -> one partial (value, sample) per item.
+// ---------------------------------------------------------------------------
+template <typename Real, class PL>
+__global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
+  constexpr int LP = lds_padded_len(PL::N2);
+  constexpr int NW = PL::T2 / 64;
+  __shared__ cplx<Real> lds[PL::RW * LP];
+  __shared__ cplx<Real> tw[PL::N2];
+  __shared__ Real red_g[NW > 0 ? NW : 1];
+  __shared__ int red_j[NW > 0 ? NW : 1];
+  const int tid = threadIdx.x;
+  for (int m = tid; m < PL::N2; m += PL::T2) tw[m] = twiddle<Real>(m, PL::N2);
+  __syncthreads();
+  int cnt = *a.count - a.chunk_begin;
+  cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
+  const int items = cnt * PL::TILES2;
+  const int p = tid % PL::P2, r = tid / PL::P2;
+  cplx<Real>* buf = lds + r * LP;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    const int slot = item / PL::TILES2;
+    const int tile = item - slot * PL::TILES2;
+    const int e = a.list[a.chunk_begin + slot];
+    const cplx<Real>* ws = (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
+    cplx<Real> v[2][PL::E2];
+    pass2_load<Real, PL>(v, ws, tile, r, p);
+    run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, buf, tw, p);
+    Real g;
+    int j;
+    pass2_best<Real, PL>(v, tile, r, p, g, j);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      const Real go = __shfl_xor(g, off, 64);
+      const int jo = __shfl_xor(j, off, 64);
+      if (better(go, jo, g, j)) {
+        g = go;
+        j = jo;
+      }
+    }
+    if (lane == 0) {
+      red_g[wave] = g;
+      red_j[wave] = j;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      for (int w = 1; w < NW; ++w)
+        if (better(red_g[w], red_j[w], g, j)) {
+          g = red_g[w];
+          j = red_j[w];
+        }
+      ((Real*)a.part_g)[(int64_t)e * kMaxTiles2 + tile] = g;
+      a.part_j[(int64_t)e * kMaxTiles2 + tile] = j;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: one thread per point, maximum over its pass-2 partials.
+// ---------------------------------------------------------------------------
+template <typename Real>
+__global__ void k_finalize(const EvalDesc* __restrict__ evals, const SegDesc* __restrict__ segs,
+                           const Real* __restrict__ part_g, const int32_t* __restrict__ part_j, int n,
+                           const int32_t* __restrict__ plan_tiles2, double* __restrict__ fitness,
+                           int32_t* __restrict__ argmax) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const EvalDesc& ev = evals[e];
+  if (ev.status == 0) {
+    fitness[e] = -INFINITY;
+    argmax[e] = -1;
+    return;
+  }
+  if (ev.status != 1) {
+    fitness[e] = NAN;
+    argmax[e] = -2;
+    return;
+  }
+  const int nt = plan_tiles2[ev.plan];
+  Real g = part_g[(int64_t)e * kMaxTiles2];
+  int j = part_j[(int64_t)e * kMaxTiles2];
+  for (int t = 1; t < nt; ++t) {
+    const Real go = part_g[(int64_t)e * kMaxTiles2 + t];
+    const int jo = part_j[(int64_t)e * kMaxTiles2 + t];
+    if (better(go, jo, g, j)) {
+      g = go;
+      j = jo;
+    }
+  }
+  fitness[e] = (double)g;
+  argmax[e] = j;
+}
+
+}  // namespace fcas

@@ -1,0 +1,579 @@
+// fcas_api.cpp -- the C ABI (include/fcas.h): argument validation on the
+// host, the context (network, tables, workspace), the segment registry and the
+// launch sequence of each entry point.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fcas.h"
+#include "grad_kernels.hpp"
+#include "launch.hpp"
+#include "pso_kernels.hpp"
+
+using namespace fcas;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FCAS_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct TimedPair {
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct fcas_ctx {
+  int device = 0;
+  fcas_network net{};
+  fcas_config cfg{};
+  int prec = 0;          // 0 float, 1 double
+  size_t elt = 8;        // bytes of one complex element of the FFT path
+  NetDesc h_net{};
+  NetDesc* d_net = nullptr;
+  std::vector<SegDesc> h_segs;
+  SegDesc* d_segs = nullptr;
+  std::vector<void*> seg_y;
+  std::vector<double*> seg_b;
+  EvalDesc* d_evals = nullptr;
+  int32_t* d_lists = nullptr;    // [kNumPlans][max_batch]
+  int32_t* d_counts = nullptr;   // [kNumPlans]
+  void* d_part_g = nullptr;      // [max_batch][kMaxTiles2]
+  int32_t* d_part_j = nullptr;
+  int32_t* d_plan_tiles2 = nullptr;
+  int32_t* d_err = nullptr;
+  double* d_sigma2 = nullptr;    // [FCAS_MAX_DET] scratch for segment registration
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  GradBuffers grad{};
+  int plan_refs[kNumPlans] = {0};   // registered segments per plan
+  bool timing = false;
+  std::vector<TimedPair> t_pass1, t_pass2;
+  int grid_cap = 2048;
+};
+
+namespace {
+
+bool finite_all(const double* v, int n) {
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// In-band bins f_* < k/T <= min(f_high, fs/2), 1 <= k < N/2.
+void band(const fcas_config& c, int64_t n, int* k_lo, int* k_hi) {
+  const double T = (double)n / c.fs_hz;
+  const int64_t lo = (int64_t)std::floor(c.f_low_hz * T) + 1;
+  int64_t hi = (int64_t)std::floor(c.f_high_hz * T);
+  if (hi > n / 2 - 1) hi = n / 2 - 1;
+  *k_lo = (int)lo;
+  *k_hi = (int)hi;
+}
+
+int validate_network(const fcas_network* net) {
+  if (!net) return fail(FCAS_EINVAL, "network is NULL");
+  if (net->n_det < 1 || net->n_det > FCAS_MAX_DET)
+    return fail(FCAS_EINVAL, "n_det must be in [1, %d], got %d", FCAS_MAX_DET, net->n_det);
+  for (int i = 0; i < net->n_det; ++i) {
+    if (!finite_all(net->pos_m[i], 3) || !finite_all(&net->tensor[i][0][0], 9))
+      return fail(FCAS_EINVAL, "detector %d has a non-finite position or tensor", i);
+  }
+  return FCAS_OK;
+}
+
+int validate_config(const fcas_config* c) {
+  if (!c) return fail(FCAS_EINVAL, "config is NULL");
+  if (!(c->fs_hz > 0) || !std::isfinite(c->fs_hz)) return fail(FCAS_EINVAL, "fs_hz must be positive");
+  if (!(c->f_low_hz > 0) || !(c->f_high_hz > c->f_low_hz) || !std::isfinite(c->f_high_hz))
+    return fail(FCAS_EINVAL, "need 0 < f_low_hz < f_high_hz");
+  if (c->precision != FCAS_MIXED && c->precision != FCAS_FP64)
+    return fail(FCAS_EINVAL, "precision must be FCAS_MIXED or FCAS_FP64");
+  if (c->max_batch < 1 || c->max_batch > (1 << 24)) return fail(FCAS_EINVAL, "max_batch must be in [1, 2^24]");
+  if (c->max_segments < 1 || c->max_segments > (1 << 20))
+    return fail(FCAS_EINVAL, "max_segments must be in [1, 2^20]");
+  if (plan_for_length(c->max_samples) < 0)
+    return fail(FCAS_EUNSUPPORTED_N, "max_samples %lld has no FFT plan", (long long)c->max_samples);
+  if (c->workspace_bytes < 0) return fail(FCAS_EINVAL, "workspace_bytes must be >= 0");
+  for (int d = 0; d < 4; ++d) {
+    if (!std::isfinite(c->box_lo[d]) || !std::isfinite(c->box_hi[d]) || !(c->box_hi[d] >= c->box_lo[d]))
+      return fail(FCAS_EINVAL, "search box coordinate %d must satisfy lo <= hi (finite)", d);
+  }
+  if (!(c->box_lo[2] > 0) || !(c->box_lo[3] > 0)) return fail(FCAS_EINVAL, "chirp times must be positive");
+  return FCAS_OK;
+}
+
+int validate_batch(const fcas_ctx* ctx, int32_t n, const void* theta, const void* seg, const void* f,
+                   const void* j) {
+  if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
+  if (n < 0) return fail(FCAS_EINVAL, "n must be >= 0, got %d", n);
+  if (n > ctx->cfg.max_batch)
+    return fail(FCAS_ECAPACITY, "n = %d exceeds max_batch = %d", n, ctx->cfg.max_batch);
+  if (n > 0 && (!theta || !seg || !f || !j)) return fail(FCAS_EINVAL, "NULL device pointer");
+  return FCAS_OK;
+}
+
+int free_all(fcas_ctx* c) {
+  for (void* p : c->seg_y) if (p) hipFree(p);
+  for (double* p : c->seg_b) if (p) hipFree(p);
+  void* bufs[] = {c->d_net, c->d_segs, c->d_evals, c->d_lists, c->d_counts, c->d_part_g,
+                  c->d_part_j, c->d_plan_tiles2, c->d_err, c->d_sigma2, c->d_ws};
+  for (void* p : bufs) if (p) hipFree(p);
+  free_grad_buffers(c->grad);
+  for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+  for (auto& t : c->t_pass2) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+  return FCAS_OK;
+}
+
+template <typename T>
+int dev_alloc(T** p, size_t bytes) {
+  hipError_t e = hipMalloc((void**)p, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(FCAS_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return FCAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fcas_last_error(void) { return g_last_error.c_str(); }
+
+int fcas_supported_n(int64_t n_samples) { return plan_for_length(n_samples) >= 0 ? 1 : 0; }
+
+int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fcas_ctx** out) {
+  g_last_error.clear();
+  if (!out) return fail(FCAS_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_network(net);
+  if (rc) return rc;
+  rc = validate_config(cfg);
+  if (rc) return rc;
+  {
+    int k_lo, k_hi;
+    band(*cfg, cfg->max_samples, &k_lo, &k_hi);
+    if (k_lo > k_hi) return fail(FCAS_EINVAL, "empty band at max_samples");
+  }
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev <= 0) return fail(FCAS_EHIP, "no HIP device available");
+  if (device < 0 || device >= ndev) return fail(FCAS_EINVAL, "device %d out of range [0, %d)", device, ndev);
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+
+  fcas_ctx* c = new fcas_ctx();
+  c->device = device;
+  c->net = *net;
+  c->cfg = *cfg;
+  c->prec = cfg->precision == FCAS_FP64 ? 1 : 0;
+  c->elt = c->prec ? 16 : 8;
+  NetDesc& h = c->h_net;
+  h.n_det = net->n_det;
+  h.max_segments = cfg->max_segments;
+  std::memcpy(h.pos, net->pos_m, sizeof h.pos);
+  std::memcpy(h.ten, net->tensor, sizeof h.ten);
+  std::memcpy(h.box_lo, cfg->box_lo, sizeof h.box_lo);
+  std::memcpy(h.box_hi, cfg->box_hi, sizeof h.box_hi);
+  h.f_star = cfg->f_low_hz;
+  const int B = cfg->max_batch;
+  const size_t slot_bytes = 2 * (size_t)cfg->max_samples * c->elt;
+  size_t ws = cfg->workspace_bytes > 0 ? (size_t)cfg->workspace_bytes : (size_t)B * slot_bytes;
+  const size_t ws_default_cap = (size_t)8 << 30;
+  if (cfg->workspace_bytes == 0 && ws > ws_default_cap) ws = ws_default_cap;
+  if (ws < slot_bytes) {
+    delete c;
+    return fail(FCAS_EINVAL, "workspace_bytes %zu below one evaluation (%zu)", ws, slot_bytes);
+  }
+  c->ws_bytes = ws;
+  c->h_segs.assign(cfg->max_segments, SegDesc{});
+  c->seg_y.assign(cfg->max_segments, nullptr);
+  c->seg_b.assign(cfg->max_segments, nullptr);
+  const size_t part_elt = c->prec ? 8 : 4;
+  if ((rc = dev_alloc(&c->d_net, sizeof(NetDesc))) || (rc = dev_alloc(&c->d_segs, sizeof(SegDesc) * cfg->max_segments)) ||
+      (rc = dev_alloc(&c->d_evals, sizeof(EvalDesc) * B)) ||
+      (rc = dev_alloc(&c->d_lists, sizeof(int32_t) * (size_t)kNumPlans * B)) ||
+      (rc = dev_alloc(&c->d_counts, sizeof(int32_t) * kNumPlans)) ||
+      (rc = dev_alloc(&c->d_part_g, part_elt * (size_t)B * kMaxTiles2)) ||
+      (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * kMaxTiles2)) ||
+      (rc = dev_alloc(&c->d_plan_tiles2, sizeof(int32_t) * kNumPlans)) ||
+      (rc = dev_alloc(&c->d_err, sizeof(int32_t))) || (rc = dev_alloc(&c->d_sigma2, sizeof(double) * FCAS_MAX_DET)) ||
+      (rc = dev_alloc(&c->d_ws, ws)) || (rc = alloc_grad_buffers(c->grad, B, net->n_det))) {
+    std::string msg = g_last_error;
+    free_all(c);
+    delete c;
+    g_last_error = msg;
+    return rc;
+  }
+  int32_t tiles2[kNumPlans];
+  for (int i = 0; i < kNumPlans; ++i) tiles2[i] = kPlans[i].tiles2[c->prec];
+  if ((e = hipMemcpy(c->d_net, &h, sizeof(NetDesc), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_segs, c->h_segs.data(), sizeof(SegDesc) * cfg->max_segments, hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(c->d_plan_tiles2, tiles2, sizeof tiles2, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemset(c->d_err, 0, sizeof(int32_t))) != hipSuccess ||
+      (e = hipMemset(c->d_counts, 0, sizeof(int32_t) * kNumPlans)) != hipSuccess) {
+    rc = hip_fail(e, "context initialisation");
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return FCAS_OK;
+}
+
+int fcas_destroy(fcas_ctx* ctx) {
+  if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  free_all(ctx);
+  delete ctx;
+  return FCAS_OK;
+}
+
+size_t fcas_workspace_bytes(const fcas_ctx* ctx) { return ctx ? ctx->ws_bytes : 0; }
+
+int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples, const double* d_xf, const double* d_psd,
+                     void* hip_stream) {
+  if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
+  if (seg_id < 0 || seg_id >= ctx->cfg.max_segments)
+    return fail(FCAS_ENOSEG, "segment id %d out of range [0, %d)", seg_id, ctx->cfg.max_segments);
+  const int plan = plan_for_length(n_samples);
+  if (plan < 0) return fail(FCAS_EUNSUPPORTED_N, "segment length %lld has no FFT plan", (long long)n_samples);
+  if (n_samples > ctx->cfg.max_samples)
+    return fail(FCAS_EINVAL, "segment length %lld exceeds max_samples %lld", (long long)n_samples,
+                (long long)ctx->cfg.max_samples);
+  if (!d_xf || !d_psd) return fail(FCAS_EINVAL, "NULL device pointer");
+  int k_lo, k_hi;
+  band(ctx->cfg, n_samples, &k_lo, &k_hi);
+  if (k_lo > k_hi) return fail(FCAS_EINVAL, "empty band for %lld samples", (long long)n_samples);
+  hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int D = ctx->net.n_det;
+  const int K = k_hi - k_lo + 1;
+  const int64_t half = n_samples / 2 + 1;
+  const double df = ctx->cfg.fs_hz / (double)n_samples;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  // a re-registered segment replaces the old buffers
+  if (ctx->seg_y[seg_id]) {
+    hipFree(ctx->seg_y[seg_id]);
+    hipFree(ctx->seg_b[seg_id]);
+    ctx->seg_y[seg_id] = nullptr;
+    ctx->seg_b[seg_id] = nullptr;
+    ctx->plan_refs[ctx->h_segs[seg_id].plan]--;
+    ctx->h_segs[seg_id] = SegDesc{};
+  }
+  void* y = nullptr;
+  double* b = nullptr;
+  int rc;
+  if ((rc = dev_alloc(&y, (size_t)K * D * ctx->elt))) return rc;
+  if ((rc = dev_alloc(&b, (size_t)K * sizeof(double)))) {
+    hipFree(y);
+    return rc;
+  }
+  if ((e = launch_segment_sigma(d_psd, D, half, k_lo, k_hi, df, ctx->d_sigma2, s)) != hipSuccess ||
+      (e = launch_segment_prep(ctx->prec, d_xf, d_psd, ctx->d_sigma2, D, half, k_lo, k_hi, df, ctx->cfg.f_low_hz, y,
+                               b, s)) != hipSuccess) {
+    hipFree(y);
+    hipFree(b);
+    return hip_fail(e, "segment preparation launch");
+  }
+  double sigma2[FCAS_MAX_DET];
+  if ((e = hipMemcpyAsync(sigma2, ctx->d_sigma2, sizeof(double) * D, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess) {
+    hipFree(y);
+    hipFree(b);
+    return hip_fail(e, "segment preparation");
+  }
+  SegDesc sd{};
+  sd.y = y;
+  sd.b = b;
+  sd.n = n_samples;
+  sd.k_lo = k_lo;
+  sd.k_hi = k_hi;
+  sd.plan = plan;
+  sd.registered = 1;
+  sd.df = df;
+  for (int i = 0; i < D; ++i) {
+    if (!(sigma2[i] > 0) || !std::isfinite(sigma2[i])) {
+      hipFree(y);
+      hipFree(b);
+      return fail(FCAS_EINVAL, "template norm of detector %d is not positive and finite (check the PSD)", i);
+    }
+    sd.sigma[i] = std::sqrt(sigma2[i]);
+  }
+  if ((e = hipMemcpy(ctx->d_segs + seg_id, &sd, sizeof sd, hipMemcpyHostToDevice)) != hipSuccess) {
+    hipFree(y);
+    hipFree(b);
+    return hip_fail(e, "segment descriptor upload");
+  }
+  ctx->h_segs[seg_id] = sd;
+  ctx->seg_y[seg_id] = y;
+  ctx->seg_b[seg_id] = b;
+  ctx->plan_refs[plan]++;
+  return FCAS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t s, int pass, int plan,
+                        const PassArgs& a, int grid) {
+  TimedPair tp{};
+  if (ctx->timing) {
+    hipEventCreate(&tp.a);
+    hipEventCreate(&tp.b);
+    hipEventRecord(tp.a, s);
+  }
+  hipError_t e = pass == 1 ? launch_pass1(ctx->prec, plan, a, grid, s) : launch_pass2(ctx->prec, plan, a, grid, s);
+  if (ctx->timing) {
+    hipEventRecord(tp.b, s);
+    rec.push_back(tp);
+  }
+  return e;
+}
+
+// Enqueues set-up, both FFT passes of every plan in use, and finalize.
+int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
+                 int32_t* d_argmax, hipStream_t s) {
+  hipError_t e;
+  if ((e = launch_zero_i32(ctx->d_counts, kNumPlans, s)) != hipSuccess) return hip_fail(e, "zero counters");
+  if ((e = launch_setup(ctx->d_net, ctx->d_segs, d_theta, d_seg, n, ctx->d_evals, ctx->d_lists, ctx->d_counts,
+                        ctx->cfg.max_batch, ctx->d_err, s)) != hipSuccess)
+    return hip_fail(e, "set-up launch");
+  for (int plan = 0; plan < kNumPlans; ++plan) {
+    if (ctx->plan_refs[plan] <= 0) continue;
+    const PlanInfo& pi = kPlans[plan];
+    const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
+    int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
+    if (cap < 1) cap = 1;
+    PassArgs a{};
+    a.segs = ctx->d_segs;
+    a.evals = ctx->d_evals;
+    a.list = ctx->d_lists + (size_t)plan * ctx->cfg.max_batch;
+    a.count = ctx->d_counts + plan;
+    a.ws = ctx->d_ws;
+    a.part_g = ctx->d_part_g;
+    a.part_j = ctx->d_part_j;
+    a.n_det = ctx->net.n_det;
+    a.cap = cap;
+    for (int begin = 0; begin < n; begin += cap) {
+      a.chunk_begin = begin;
+      const int m = std::min(cap, n - begin);
+      const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid_cap);
+      const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid_cap);
+      if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
+      if ((e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
+    }
+  }
+  if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->d_plan_tiles2,
+                           d_fitness, d_argmax, s)) != hipSuccess)
+    return hip_fail(e, "finalize launch");
+  return FCAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fitness_eval_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
+                       int32_t* d_argmax, void* hip_stream) {
+  int rc = validate_batch(ctx, n, d_theta, d_seg, d_fitness, d_argmax);
+  if (rc) return rc;
+  if (n == 0) return FCAS_OK;
+  hipSetDevice(ctx->device);
+  return enqueue_eval(ctx, n, d_theta, d_seg, d_fitness, d_argmax, (hipStream_t)hip_stream);
+}
+
+int fitness_grad_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
+                       int32_t* d_argmax, double* d_grad, void* hip_stream) {
+  int rc = validate_batch(ctx, n, d_theta, d_seg, d_fitness, d_argmax);
+  if (rc) return rc;
+  if (n > 0 && !d_grad) return fail(FCAS_EINVAL, "NULL gradient pointer");
+  if (n == 0) return FCAS_OK;
+  hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  if ((rc = enqueue_eval(ctx, n, d_theta, d_seg, d_fitness, d_argmax, s))) return rc;
+  hipError_t e = launch_gradient(ctx->prec, ctx->grad, ctx->d_net, ctx->d_segs, ctx->d_evals, d_theta, d_argmax, n,
+                                 ctx->net.n_det, d_grad, s);
+  if (e != hipSuccess) return hip_fail(e, "gradient launch");
+  return FCAS_OK;
+}
+
+int fcas_inject(fcas_ctx* ctx, int64_t n_samples, const double* params, double snr, const double* d_psd,
+                double* d_xf, void* hip_stream) {
+  if (!ctx || !params || !d_psd || !d_xf) return fail(FCAS_EINVAL, "NULL argument");
+  if (!finite_all(params, 8) || !std::isfinite(snr) || snr < 0) return fail(FCAS_EINVAL, "non-finite parameter");
+  if (!(params[2] > 0) || !(params[3] > 0)) return fail(FCAS_EINVAL, "chirp times must be positive");
+  if (params[6] < -1.0 || params[6] > 1.0) return fail(FCAS_EINVAL, "cos_iota must be in [-1, 1]");
+  if (n_samples < 4 || (n_samples & 1)) return fail(FCAS_EINVAL, "n_samples must be even and >= 4");
+  int k_lo, k_hi;
+  band(ctx->cfg, n_samples, &k_lo, &k_hi);
+  if (k_lo > k_hi) return fail(FCAS_EINVAL, "empty band for %lld samples", (long long)n_samples);
+  hipSetDevice(ctx->device);
+  hipError_t e = launch_inject(ctx->h_net, params, snr, n_samples, k_lo, k_hi, ctx->cfg.fs_hz / (double)n_samples,
+                               d_psd, ctx->d_sigma2, d_xf, (hipStream_t)hip_stream);
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "injection launch");
+}
+
+int fcas_device_error(fcas_ctx* ctx, int32_t* flags_out) {
+  if (!ctx || !flags_out) return fail(FCAS_EINVAL, "NULL argument");
+  hipSetDevice(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  if ((e = hipMemcpy(flags_out, ctx->d_err, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "read error flags");
+  if ((e = hipMemset(ctx->d_err, 0, sizeof(int32_t))) != hipSuccess) return hip_fail(e, "clear error flags");
+  return FCAS_OK;
+}
+
+int fcas_set_timing(fcas_ctx* ctx, int enable) {
+  if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
+  ctx->timing = enable != 0;
+  return FCAS_OK;
+}
+
+int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t* launches) {
+  if (!ctx || !which || !total_ms || !launches) return fail(FCAS_EINVAL, "NULL argument");
+  std::vector<TimedPair>* rec = nullptr;
+  if (!std::strcmp(which, "pass1")) rec = &ctx->t_pass1;
+  else if (!std::strcmp(which, "pass2")) rec = &ctx->t_pass2;
+  else return fail(FCAS_EINVAL, "unknown kernel name '%s' (timed: pass1, pass2)", which);
+  hipSetDevice(ctx->device);
+  double tot = 0.0;
+  for (auto& t : *rec) {
+    hipError_t e = hipEventSynchronize(t.b);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, t.a, t.b);
+    tot += ms;
+    hipEventDestroy(t.a);
+    hipEventDestroy(t.b);
+  }
+  *total_ms = tot;
+  *launches = (int64_t)rec->size();
+  rec->clear();
+  return FCAS_OK;
+}
+
+}  // extern "C"
+
+// precision dispatch of the pass launchers (the instantiations live in eval_f32.hip / eval_f64.hip)
+namespace fcas {
+hipError_t launch_pass1_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_finalize_f32(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
+                               double*, int32_t*, hipStream_t);
+hipError_t launch_finalize_f64(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
+                               double*, int32_t*, hipStream_t);
+
+hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
+  return precision ? launch_pass1_f64(plan, a, grid, s) : launch_pass1_f32(plan, a, grid, s);
+}
+hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
+  return precision ? launch_pass2_f64(plan, a, grid, s) : launch_pass2_f32(plan, a, grid, s);
+}
+hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
+                           const int32_t* part_j, int n, const int32_t* plan_tiles2, double* fitness,
+                           int32_t* argmax, hipStream_t s) {
+  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, plan_tiles2, fitness, argmax, s)
+                   : launch_finalize_f32(evals, segs, part_g, part_j, n, plan_tiles2, fitness, argmax, s);
+}
+}  // namespace fcas
+
+namespace {
+
+int make_pso(const fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, PsoDev* d) {
+  if (!ctx || !p || !s) return fail(FCAS_EINVAL, "NULL argument");
+  if (p->n_runs < 1 || p->n_runs > (1 << 20)) return fail(FCAS_EINVAL, "n_runs must be in [1, 2^20]");
+  if (p->n_particles < 1 || p->n_particles > 1024) return fail(FCAS_EINVAL, "n_particles must be in [1, 1024]");
+  if (p->n_iter < 1) return fail(FCAS_EINVAL, "n_iter must be >= 1");
+  const double pr[5] = {p->w0, p->w1, p->c1, p->c2, p->vmax};
+  if (!finite_all(pr, 5) || !(p->vmax > 0)) return fail(FCAS_EINVAL, "PSO constants must be finite, vmax > 0");
+  if (!s->x || !s->v || !s->pbest_x || !s->pbest_f || !s->pbest_j || !s->best_x || !s->best_f || !s->best_j)
+    return fail(FCAS_EINVAL, "NULL swarm state array");
+  d->n_runs = p->n_runs;
+  d->n_particles = p->n_particles;
+  d->n_iter = p->n_iter;
+  d->w0 = p->w0;
+  d->w1 = p->w1;
+  d->c1 = p->c1;
+  d->c2 = p->c2;
+  d->vmax = p->vmax;
+  d->seed = p->seed;
+  for (int k = 0; k < 4; ++k) {
+    d->lo[k] = ctx->cfg.box_lo[k];
+    d->span[k] = ctx->cfg.box_hi[k] - ctx->cfg.box_lo[k];
+  }
+  d->x = s->x;
+  d->v = s->v;
+  d->pbest_x = s->pbest_x;
+  d->pbest_f = s->pbest_f;
+  d->pbest_j = s->pbest_j;
+  d->best_x = s->best_x;
+  d->best_f = s->best_f;
+  d->best_j = s->best_j;
+  return FCAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pso_init(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, double* d_theta_out,
+             void* hip_stream) {
+  PsoDev d{};
+  int rc = make_pso(ctx, p, s, &d);
+  if (rc) return rc;
+  if (!d_theta_out) return fail(FCAS_EINVAL, "NULL theta output");
+  hipSetDevice(ctx->device);
+  hipError_t e = launch_pso_init(d, d_theta_out, (hipStream_t)hip_stream);
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_init launch");
+}
+
+int pso_step(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, const double* d_fitness,
+             const int32_t* d_argmax, int32_t iter, double* d_theta_next, void* hip_stream) {
+  PsoDev d{};
+  int rc = make_pso(ctx, p, s, &d);
+  if (rc) return rc;
+  if (!d_fitness || !d_argmax || !d_theta_next) return fail(FCAS_EINVAL, "NULL device pointer");
+  if (iter < 0) return fail(FCAS_EINVAL, "iter must be >= 0");
+  hipSetDevice(ctx->device);
+  hipError_t e = launch_pso_step(d, d_fitness, d_argmax, iter, d_theta_next, (hipStream_t)hip_stream);
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_step launch");
+}
+
+int pso_best(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, double* d_out_f,
+             double* d_out_theta, int32_t* d_out_j, int32_t* d_out_run, void* hip_stream) {
+  PsoDev d{};
+  int rc = make_pso(ctx, p, s, &d);
+  if (rc) return rc;
+  if (!d_out_f || !d_out_theta || !d_out_j || !d_out_run) return fail(FCAS_EINVAL, "NULL device pointer");
+  hipSetDevice(ctx->device);
+  hipError_t e = launch_pso_best(d, d_out_f, d_out_theta, d_out_j, d_out_run, (hipStream_t)hip_stream);
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_best launch");
+}
+
+}  // extern "C"

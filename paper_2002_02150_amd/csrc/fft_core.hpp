@@ -1,0 +1,213 @@
+// fft_core.hpp -- register/LDS building blocks of the batched inverse FFTs.
+//
+// Host- and device-callable so that the CPU emulator (tests) runs exactly the
+// same index arithmetic and butterflies as the gfx950 kernels.
+//
+// Sign convention: every transform here is the un-normalised inverse DFT
+//   X[j] = sum_k x[k] exp(+2 pi i k j / L),
+// which turns the frequency-domain integrand into the matched-filter output at
+// every coalescence sample (Sec. II.C: maximisation over t_c by FFT).
+#pragma once
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define FCAS_HD __host__ __device__ __forceinline__
+#else
+#include <cmath>
+#define FCAS_HD inline
+#endif
+
+namespace fcas {
+
+template <typename R>
+struct cplx {
+  R x, y;
+};
+
+template <typename R> FCAS_HD cplx<R> mk(R a, R b) { cplx<R> c; c.x = a; c.y = b; return c; }
+template <typename R> FCAS_HD cplx<R> add(cplx<R> a, cplx<R> b) { return mk<R>(a.x + b.x, a.y + b.y); }
+template <typename R> FCAS_HD cplx<R> sub(cplx<R> a, cplx<R> b) { return mk<R>(a.x - b.x, a.y - b.y); }
+template <typename R> FCAS_HD cplx<R> mul(cplx<R> a, cplx<R> b) {
+  return mk<R>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+template <typename R> FCAS_HD cplx<R> scale(cplx<R> a, R s) { return mk<R>(a.x * s, a.y * s); }
+// multiply by +i
+template <typename R> FCAS_HD cplx<R> mul_i(cplx<R> a) { return mk<R>(-a.y, a.x); }
+// multiply by -i
+template <typename R> FCAS_HD cplx<R> mul_mi(cplx<R> a) { return mk<R>(a.y, -a.x); }
+template <typename R> FCAS_HD R norm2(cplx<R> a) { return a.x * a.x + a.y * a.y; }
+
+// ---------------------------------------------------------------------------
+// sin(2 pi r), cos(2 pi r) for r in revolutions, float.
+// Octant reduction (exact in binary floating point) followed by the Taylor
+// series of sin (to t^11) and cos (to t^10) on |2 pi t| <= pi/4; truncation
+// error below 1.2e-10, far under float rounding.
+// ---------------------------------------------------------------------------
+FCAS_HD void sincos_rev(float r, float* s, float* c) {
+  float q = rintf(4.0f * r);           // nearest quarter turn
+  float t = r - 0.25f * q;             // |t| <= 1/8, exact
+  float u = t * t;
+  // coefficients (2 pi)^n / n! with alternating signs
+  const float S1 = 6.283185307179586f, S3 = -41.341702240399755f, S5 = 81.60524927607504f,
+              S7 = -76.70585975306136f, S9 = 42.058693944897634f, S11 = -15.094642576822984f;
+  const float C2 = -19.739208802178716f, C4 = 64.93939402266828f, C6 = -85.45681720669371f,
+              C8 = 60.24464137187664f, C10 = -26.426256783374388f;
+  float sn = t * (S1 + u * (S3 + u * (S5 + u * (S7 + u * (S9 + u * S11)))));
+  float cs = 1.0f + u * (C2 + u * (C4 + u * (C6 + u * (C8 + u * C10))));
+  int qi = ((int)q) & 3;
+  float so = sn, co = cs;
+  if (qi == 1) { so = cs; co = -sn; }
+  else if (qi == 2) { so = -sn; co = -cs; }
+  else if (qi == 3) { so = -cs; co = sn; }
+  *s = so;
+  *c = co;
+}
+
+// double version for the FP64 path: sin(2 pi r), cos(2 pi r)
+FCAS_HD void sincos_rev(double r, double* s, double* c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  sincospi(2.0 * r, s, c);
+#else
+  const double tp = 6.283185307179586476925286766559;
+  *s = std::sin(tp * r);
+  *c = std::cos(tp * r);
+#endif
+}
+
+// e^{+2 pi i m / L} for integer 0 <= m < L
+template <typename R>
+FCAS_HD cplx<R> twiddle(int m, int L) {
+  R s, c;
+  R r = (R)m / (R)L;
+  if (r > (R)0.5) r -= (R)1;
+  sincos_rev(r, &s, &c);
+  return mk<R>(c, s);
+}
+
+// ---------------------------------------------------------------------------
+// Small inverse DFTs in registers: x[0..R) -> X[0..R), X[j] = sum_p x[p] w_R^{pj}
+// ---------------------------------------------------------------------------
+template <typename T>
+FCAS_HD void dft2(cplx<T>& a, cplx<T>& b) {
+  cplx<T> t = a;
+  a = add(t, b);
+  b = sub(t, b);
+}
+
+template <typename T>
+FCAS_HD void dft4(cplx<T>& x0, cplx<T>& x1, cplx<T>& x2, cplx<T>& x3) {
+  cplx<T> a = add(x0, x2), b = sub(x0, x2), c = add(x1, x3), d = mul_i(sub(x1, x3));
+  x0 = add(a, c);
+  x2 = sub(a, c);
+  x1 = add(b, d);
+  x3 = sub(b, d);
+}
+
+template <typename T>
+FCAS_HD void dft3(cplx<T>& x0, cplx<T>& x1, cplx<T>& x2) {
+  // w = e^{+2 pi i/3} = -1/2 + i sqrt(3)/2
+  const T h = (T)0.86602540378443864676;
+  cplx<T> s = add(x1, x2), d = sub(x1, x2);
+  cplx<T> m = sub(x0, scale(s, (T)0.5));
+  cplx<T> r = scale(mul_i(d), h);
+  x0 = add(x0, s);
+  x1 = add(m, r);
+  x2 = sub(m, r);
+}
+
+template <typename T>
+FCAS_HD void dft8(cplx<T>* x) {
+  // even / odd split, then combine with w_8^j
+  cplx<T> e0 = x[0], e1 = x[2], e2 = x[4], e3 = x[6];
+  cplx<T> o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
+  dft4(e0, e1, e2, e3);
+  dft4(o0, o1, o2, o3);
+  const T r = (T)0.70710678118654752440;
+  cplx<T> t1 = scale(mk<T>(o1.x - o1.y, o1.x + o1.y), r);   // w8^1 = (1+i)/sqrt2
+  cplx<T> t2 = mul_i(o2);                                      // w8^2 = i
+  cplx<T> t3 = scale(mk<T>(-o3.x - o3.y, o3.x - o3.y), r);  // w8^3 = (-1+i)/sqrt2
+  x[0] = add(e0, o0); x[4] = sub(e0, o0);
+  x[1] = add(e1, t1); x[5] = sub(e1, t1);
+  x[2] = add(e2, t2); x[6] = sub(e2, t2);
+  x[3] = add(e3, t3); x[7] = sub(e3, t3);
+}
+
+template <typename T>
+FCAS_HD void dft16(cplx<T>* x) {
+  // 16 = 4 x 4: p = 4a + b, j = c + 4d.
+  // inner DFT4 over a for each b, twiddle w16^{b c}, outer DFT4 over b for each c.
+  cplx<T> y[16];
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    cplx<T> a0 = x[b], a1 = x[b + 4], a2 = x[b + 8], a3 = x[b + 12];
+    dft4(a0, a1, a2, a3);
+    y[4 * b + 0] = a0; y[4 * b + 1] = a1; y[4 * b + 2] = a2; y[4 * b + 3] = a3;   // y[4b + c]
+  }
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173;
+  const T r2 = (T)0.70710678118654752440;
+  // w16^m = e^{+2 pi i m /16}
+  const cplx<T> w1 = mk<T>(c1, s1), w2 = mk<T>(r2, r2), w3 = mk<T>(s1, c1);
+  const cplx<T> w6 = mk<T>(-r2, r2), w9 = mk<T>(-c1, -s1);
+  // b=1: c=1,2,3 -> w^1, w^2, w^3 ; b=2: w^2, w^4, w^6 ; b=3: w^3, w^6, w^9
+  y[5] = mul(y[5], w1); y[6] = mul(y[6], w2); y[7] = mul(y[7], w3);
+  y[9] = mul(y[9], w2); y[10] = mul_i(y[10]); y[11] = mul(y[11], w6);
+  y[13] = mul(y[13], w3); y[14] = mul(y[14], w6); y[15] = mul(y[15], w9);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cplx<T> b0 = y[c], b1 = y[4 + c], b2 = y[8 + c], b3 = y[12 + c];
+    dft4(b0, b1, b2, b3);
+    x[c] = b0; x[c + 4] = b1; x[c + 8] = b2; x[c + 12] = b3;
+  }
+}
+
+template <int R, typename T>
+FCAS_HD void dft(cplx<T>* x) {
+  if constexpr (R == 2) {
+    dft2(x[0], x[1]);
+  } else if constexpr (R == 3) {
+    dft3(x[0], x[1], x[2]);
+  } else if constexpr (R == 4) {
+    dft4(x[0], x[1], x[2], x[3]);
+  } else if constexpr (R == 8) {
+    dft8(x);
+  } else if constexpr (R == 16) {
+    dft16(x);
+  } else {
+    static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "unsupported radix");
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Stockham schedule of one length-L transform spread over P = L/E threads,
+// each holding E elements in registers.  Register q of thread t holds element
+// t + q P both before the first stage and after the last, so the prologue
+// loads and the epilogue stores are strided by P ("natural strided order").
+//
+// Stage s with radix R and Ns = product of the earlier radices: butterfly b of
+// thread t is the virtual thread v = t + b P (0 <= v < L/R); its inputs are
+// elements v + p L/R (registers b + p E/R), twiddled by w_{Ns R}^{(v mod Ns) p},
+// and its outputs go to (v / Ns) Ns R + (v mod Ns) + p Ns.
+// ---------------------------------------------------------------------------
+template <int... Rs>
+struct Radices {
+  static constexpr int count = sizeof...(Rs);
+  static constexpr int value[sizeof...(Rs)] = {Rs...};
+  static constexpr int product() {
+    int p = 1;
+    for (int i = 0; i < count; ++i) p *= value[i];
+    return p;
+  }
+};
+
+// LDS index padding: one spare element every 16 breaks the power-of-two
+// strides of the stage writes across banks.
+FCAS_HD int lds_pad(int i) { return i + (i >> 4); }
+constexpr int lds_padded_len(int L) { return L + (L >> 4) + 1; }
+
+// position of output p of virtual thread v in stage with sub-length Ns, radix R
+FCAS_HD int stockham_dst(int v, int Ns, int R, int p) { return (v / Ns) * Ns * R + (v % Ns) + p * Ns; }
+
+// Twiddle index (into a table of w_L^m, m < L) for input p of virtual thread v.
+FCAS_HD int stockham_tw(int v, int Ns, int R, int p, int L) { return (v % Ns) * p * (L / (Ns * R)); }
+
+}  // namespace fcas

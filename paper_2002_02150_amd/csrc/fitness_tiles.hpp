@@ -1,0 +1,305 @@
+// fitness_tiles.hpp -- the two passes of the coherent-fitness evaluation, per
+// work item and per thread, written once for the gfx950 kernels and the CPU
+// emulator used by the tests.
+//
+// For one parameter point the library forms, for every in-band bin k (Sec. II.D),
+//   w^i_k = y^i_k exp(2 pi i [Phi_k + k dly_i])     (template phase and the
+//            detector delay as an exact frequency-domain shift, eq.
+//            data_template_innprod; y already carries 4 df f^-7/6 / (S sigma))
+//   W_m(k) = sum_i Q_im w^i_k,  m = 0, 1
+// where the columns of Q are an orthonormal basis of span(diag(sigma) U).  By
+// linearity the inverse FFTs of W_0, W_1 give a_m(j) = sum_i Q_im z^i_j, and
+//   Gamma^2_j = |a_0(j)|^2 + |a_1(j)|^2 = z_j^H Q Q^T z_j,
+// the log-likelihood ratio maximised over the four amplitudes (Sec. II.C).
+//
+// The length-N inverse FFT is a four-step transform, N = N1 N2,
+//   k = k1 N2 + k2,  j = j1 + N1 j2,
+//   pass 1 (per column k2): B(j1, k2) = w_N^{k2 j1} sum_{k1} W(k1 N2 + k2) w_N1^{k1 j1}
+//   pass 2 (per row j1):    a(j1 + N1 j2) = sum_{k2} B(j1, k2) w_N2^{k2 j2}
+// with B stored row-major [series][j1][k2] in the workspace.
+#pragma once
+
+#include <stdint.h>
+
+#include "fft_core.hpp"
+
+namespace fcas {
+
+constexpr int kMaxDet = 8;
+
+// Per registered segment (device resident).
+struct SegDesc {
+  const void* y;        // [K][n_det] complex (float2 or double2 by precision)
+  const double* b;      // [K] (f_k / f*)^(-1/3)
+  int64_t n;            // samples
+  int32_t k_lo, k_hi;   // inclusive in-band bins
+  int32_t plan;         // FFT plan index
+  int32_t registered;   // 1 once fcas_set_segment has completed
+  double df;            // 1 / T
+  double sigma[kMaxDet];
+};
+
+// Per parameter point, written by the set-up kernel.
+struct EvalDesc {
+  double coef[4];             // Phi_k = coef0 b^5 + coef1 b^3 + coef2 b^2 + coef3 b (cycles)
+  double dly[kMaxDet];        // Delta^i * df: delay ramp in cycles per bin
+  double q[kMaxDet][2];       // orthonormal basis of span(diag(sigma) U), FP64
+  float qf[kMaxDet][2];       // same, rounded to float
+  double v[kMaxDet][2];       // V = diag(sigma) U (kept for the gradient)
+  int32_t seg;
+  int32_t status;             // 1 evaluate, 0 outside the rectangle, -2 bad segment
+  int32_t plan;
+  int32_t rank;               // rank of V (0, 1 or 2)
+};
+
+// Network, search rectangle and band reference frequency (device resident).
+struct NetDesc {
+  int32_t n_det;
+  int32_t max_segments;
+  double pos[kMaxDet][3];
+  double ten[kMaxDet][3][3];
+  double box_lo[4], box_hi[4];
+  double f_star;
+};
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kC = 299792458.0;
+
+// ---------------------------------------------------------------------------
+// Set-up, one thread per parameter point, FP64 (chirp times, delays, antenna
+// patterns, orthonormal basis).  Sec. II.B (chirp times), Sec. II (eq.
+// detresponse: delays, antenna pattern matrix), Sec. II.C (U = F(psi = 0)).
+// ---------------------------------------------------------------------------
+FCAS_HD void setup_one(const NetDesc& net, const SegDesc& sg, const double* th, EvalDesc& ev) {
+  const double alpha = th[0], delta = th[1], tau0 = th[2], tau15 = th[3];
+  const double fs = net.f_star;
+  // chirp times -> phase coefficients (cycles)
+  const double v0 = cbrt(5.0 * tau15 / (32.0 * kPi * tau0));
+  const double eta = 1.0 / (8.0 * fs * tau15 * v0 * v0);
+  const double tau1 = 5.0 / (192.0 * kPi * fs * eta * v0 * v0 * v0) * (743.0 / 336.0 + 11.0 * eta / 4.0);
+  const double tau2 = 5.0 / (128.0 * kPi * fs * eta * v0) *
+                      (3058673.0 / 1016064.0 + 5429.0 * eta / 1008.0 + 617.0 * eta * eta / 144.0);
+  ev.coef[0] = fs * 0.6 * tau0;
+  ev.coef[1] = fs * tau1;
+  ev.coef[2] = -fs * 1.5 * tau15;
+  ev.coef[3] = fs * 3.0 * tau2;
+  // sky direction and wave axes (-alpha_hat, delta_hat)
+  double sa, ca, sd, cd;
+  sincos(alpha, &sa, &ca);
+  sincos(delta, &sd, &cd);
+  const double n[3] = {cd * ca, cd * sa, sd};
+  const double ex[3] = {sa, -ca, 0.0};
+  const double ey[3] = {-sd * ca, -sd * sa, cd};
+  double vf = 0.0;
+  for (int i = 0; i < net.n_det; ++i) {
+    const double* r = net.pos[i];
+    ev.dly[i] = -(n[0] * r[0] + n[1] * r[1] + n[2] * r[2]) / kC * sg.df;
+    double up = 0.0, uc = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        const double d = net.ten[i][a][b];
+        up += d * (ex[a] * ex[b] - ey[a] * ey[b]);
+        uc += d * (ex[a] * ey[b] + ey[a] * ex[b]);
+      }
+    ev.v[i][0] = sg.sigma[i] * up;
+    ev.v[i][1] = sg.sigma[i] * uc;
+    vf += ev.v[i][0] * ev.v[i][0] + ev.v[i][1] * ev.v[i][1];
+  }
+  // modified Gram-Schmidt (twice) on the columns of V, larger column first
+  double n0 = 0.0, n1 = 0.0;
+  for (int i = 0; i < net.n_det; ++i) {
+    n0 += ev.v[i][0] * ev.v[i][0];
+    n1 += ev.v[i][1] * ev.v[i][1];
+  }
+  const int ca_ = (n1 > n0) ? 1 : 0, cb_ = 1 - ca_;
+  const double na = sqrt(ca_ ? n1 : n0);
+  int rank = 0;
+  for (int i = 0; i < kMaxDet; ++i) ev.q[i][0] = ev.q[i][1] = 0.0;
+  if (na > 0.0) {
+    rank = 1;
+    for (int i = 0; i < net.n_det; ++i) ev.q[i][0] = ev.v[i][ca_] / na;
+    double bres[kMaxDet];
+    for (int i = 0; i < net.n_det; ++i) bres[i] = ev.v[i][cb_];
+    for (int pass = 0; pass < 2; ++pass) {
+      double dot = 0.0;
+      for (int i = 0; i < net.n_det; ++i) dot += ev.q[i][0] * bres[i];
+      for (int i = 0; i < net.n_det; ++i) bres[i] -= dot * ev.q[i][0];
+    }
+    double nb = 0.0;
+    for (int i = 0; i < net.n_det; ++i) nb += bres[i] * bres[i];
+    nb = sqrt(nb);
+    if (nb > 1e-10 * sqrt(vf)) {
+      rank = 2;
+      for (int i = 0; i < net.n_det; ++i) ev.q[i][1] = bres[i] / nb;
+    }
+  }
+  ev.rank = rank;
+  for (int i = 0; i < kMaxDet; ++i) {
+    ev.qf[i][0] = (float)ev.q[i][0];
+    ev.qf[i][1] = (float)ev.q[i][1];
+  }
+}
+
+// Common phase of bin k in cycles, b = (f_k / f*)^(-1/3): FP64 throughout.
+FCAS_HD double common_phase(const double* coef, double b) {
+  const double b2 = b * b;
+  return b * (coef[3] + b * (coef[2] + b * (coef[1] + coef[0] * b2)));
+}
+
+template <typename Real> struct Basis;
+template <> struct Basis<float> {
+  FCAS_HD static float get(const EvalDesc& e, int i, int m) { return e.qf[i][m]; }
+};
+template <> struct Basis<double> {
+  FCAS_HD static double get(const EvalDesc& e, int i, int m) { return e.q[i][m]; }
+};
+
+// W_0(k), W_1(k) for one in-band bin.  kk = k - k_lo.
+template <typename Real>
+FCAS_HD void project_bin(const EvalDesc& ev, const cplx<Real>* y, const double* bt, int n_det, int k,
+                         int kk, cplx<Real>& w0, cplx<Real>& w1) {
+  const double phc = common_phase(ev.coef, bt[kk]);
+  const double kd = (double)k;
+  const cplx<Real>* yr = y + (int64_t)kk * n_det;
+  w0 = mk<Real>(0, 0);
+  w1 = mk<Real>(0, 0);
+  for (int i = 0; i < n_det; ++i) {
+    const double ph = kd * ev.dly[i] + phc;   // cycles
+    const double r = ph - rint(ph);           // reduced to [-1/2, 1/2] in FP64
+    Real s, c;
+    sincos_rev((Real)r, &s, &c);
+    const cplx<Real> w = mul(yr[i], mk<Real>(c, s));
+    const Real q0 = Basis<Real>::get(ev, i, 0), q1 = Basis<Real>::get(ev, i, 1);
+    w0 = mk<Real>(w0.x + q0 * w.x, w0.y + q0 * w.y);
+    w1 = mk<Real>(w1.x + q1 * w.x, w1.y + q1 * w.y);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham stage for one series of one transform (see fft_core.hpp).
+// Either leaves the outputs in registers (last stage) or scatters them to the
+// transform's LDS buffer, to be gathered back in natural strided order.
+// ---------------------------------------------------------------------------
+template <typename Real, int L, int E, int R, int Ns, bool LAST>
+FCAS_HD void stage_butterflies(cplx<Real>* vs, cplx<Real>* buf, const cplx<Real>* tw, int t) {
+  constexpr int P = L / E;
+  constexpr int B = E / R;
+  static_assert(E % R == 0, "radix must divide the elements per thread");
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const int v = t + b * P;
+    cplx<Real> x[R];
+#pragma unroll
+    for (int p = 0; p < R; ++p) x[p] = vs[b + p * B];
+    if constexpr (Ns > 1) {
+#pragma unroll
+      for (int p = 1; p < R; ++p) x[p] = mul(x[p], tw[stockham_tw(v, Ns, R, p, L)]);
+    }
+    dft<R>(x);
+    if constexpr (LAST) {
+#pragma unroll
+      for (int p = 0; p < R; ++p) vs[b + p * B] = x[p];
+    } else {
+#pragma unroll
+      for (int p = 0; p < R; ++p) buf[lds_pad(stockham_dst(v, Ns, R, p))] = x[p];
+    }
+  }
+}
+
+template <typename Real, int L, int E>
+FCAS_HD void stage_gather(cplx<Real>* vs, const cplx<Real>* buf, int t) {
+  constexpr int P = L / E;
+#pragma unroll
+  for (int q = 0; q < E; ++q) vs[q] = buf[lds_pad(t + q * P)];
+}
+
+// Compile-time description of a plan: N = N1 * N2.
+//   pass 1: C columns per work item, P1 = N1 / E1 threads per column
+//   pass 2: RW rows per work item,   P2 = N2 / E2 threads per row
+template <int N1_, int E1_, class Rad1_, int C_, int N2_, int E2_, class Rad2_, int RW_>
+struct Plan {
+  static constexpr int N1 = N1_, E1 = E1_, C = C_, N2 = N2_, E2 = E2_, RW = RW_;
+  using Rad1 = Rad1_;
+  using Rad2 = Rad2_;
+  static constexpr int64_t N = (int64_t)N1 * N2;
+  static constexpr int P1 = N1 / E1, P2 = N2 / E2;
+  static constexpr int T1 = C * P1, T2 = RW * P2;           // threads per work item
+  static constexpr int TILES1 = N2 / C, TILES2 = N1 / RW;   // work items per evaluation
+  static_assert(Rad1::product() == N1, "pass-1 radices must multiply to N1");
+  static_assert(Rad2::product() == N2, "pass-2 radices must multiply to N2");
+  static_assert(N1 % E1 == 0 && N2 % E2 == 0, "elements per thread must divide the length");
+  static_assert(N2 % C == 0 && N1 % RW == 0, "tiles must divide the transform");
+};
+
+// ---------------------------------------------------------------------------
+// Pass 1, thread (c, p) of column tile `tile`: prologue into registers.
+// Register q holds k1 = p + q P1, i.e. bin k = k1 N2 + k2.
+// ---------------------------------------------------------------------------
+template <typename Real, class PL>
+FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDesc& sg, int n_det,
+                            int tile, int c, int p) {
+  const int k2 = tile * PL::C + c;
+  const cplx<Real>* y = (const cplx<Real>*)sg.y;
+#pragma unroll
+  for (int q = 0; q < PL::E1; ++q) {
+    const int k1 = p + q * PL::P1;
+    const int k = k1 * PL::N2 + k2;
+    cplx<Real> w0 = mk<Real>(0, 0), w1 = mk<Real>(0, 0);
+    if (k >= sg.k_lo && k <= sg.k_hi) project_bin<Real>(ev, y, sg.b, n_det, k, k - sg.k_lo, w0, w1);
+    v[0][q] = w0;
+    v[1][q] = w1;
+  }
+}
+
+// Pass 1 epilogue: four-step twiddle w_N^{k2 j1}, store B[m][j1][k2].
+template <typename Real, class PL>
+FCAS_HD void pass1_store(cplx<Real> (&v)[2][PL::E1], cplx<Real>* slot, int tile, int c, int p) {
+  const int k2 = tile * PL::C + c;
+#pragma unroll
+  for (int q = 0; q < PL::E1; ++q) {
+    const int j1 = p + q * PL::P1;
+    const cplx<Real> t = twiddle<Real>(k2 * j1, (int)PL::N);   // k2 j1 < N: no reduction needed
+    const int64_t o = (int64_t)j1 * PL::N2 + k2;
+    slot[o] = mul(v[0][q], t);
+    slot[PL::N + o] = mul(v[1][q], t);
+  }
+}
+
+// Pass 2 prologue: thread (r, p) of row tile `tile` loads row j1 = tile RW + r,
+// register q holds k2 = p + q P2.
+template <typename Real, class PL>
+FCAS_HD void pass2_load(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
+  const int j1 = tile * PL::RW + r;
+  const int64_t row = (int64_t)j1 * PL::N2;
+#pragma unroll
+  for (int q = 0; q < PL::E2; ++q) {
+    v[0][q] = slot[row + p + q * PL::P2];
+    v[1][q] = slot[PL::N + row + p + q * PL::P2];
+  }
+}
+
+// Pass 2 epilogue: Gamma^2_j = |a_0|^2 + |a_1|^2 at j = j1 + N1 (p + q P2);
+// the thread's largest value and, among equal values, its smallest j.
+template <typename Real, class PL>
+FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p, Real& best, int& best_j) {
+  const int j1 = tile * PL::RW + r;
+  best = (Real)-1;
+  best_j = 0x7fffffff;
+#pragma unroll
+  for (int q = 0; q < PL::E2; ++q) {
+    const Real g = norm2(v[0][q]) + norm2(v[1][q]);
+    const int j = j1 + PL::N1 * (p + q * PL::P2);
+    if (g > best) {   // j grows with q: ties keep the smaller j
+      best = g;
+      best_j = j;
+    }
+  }
+}
+
+// (g, j) ordering used by every reduction: larger g wins, then smaller j.
+template <typename Real>
+FCAS_HD bool better(Real g, int j, Real g_ref, int j_ref) {
+  return g > g_ref || (g == g_ref && j < j_ref);
+}
+
+}  // namespace fcas

@@ -1,0 +1,35 @@
+// launch.hpp -- host-side launchers shared by the C ABI layer (fcas_api.cpp)
+// and the kernel translation units.  Every launcher only enqueues work on the
+// given stream and returns the hipError_t of the launch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "eval_kernels.hpp"
+
+namespace fcas {
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
+hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* theta, const int32_t* seg_ids,
+                        int n, EvalDesc* evals, int32_t* lists, int32_t* counts, int list_stride,
+                        int32_t* err, hipStream_t s);
+
+// precision: 0 float, 1 double
+hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
+                           const int32_t* part_j, int n, const int32_t* plan_tiles2, double* fitness,
+                           int32_t* argmax, hipStream_t s);
+
+// segment preparation: sigma_i^2 = 4 df sum_B f^-7/3 / S, y = 4 df x f^-7/6 / (S sigma), b = (f/f*)^-1/3
+hipError_t launch_segment_sigma(const double* psd, int n_det, int64_t half, int k_lo, int k_hi, double df,
+                                double* sigma2_out, hipStream_t s);
+hipError_t launch_segment_prep(int precision, const double* xf, const double* psd, const double* sigma2,
+                               int n_det, int64_t half, int k_lo, int k_hi, double df, double f_star,
+                               void* y_out, double* b_out, hipStream_t s);
+
+// synthetic signal: params = (alpha, delta, tau0, tau1.5, psi, phi_c, cos_iota, t_c [s])
+hipError_t launch_inject(const NetDesc& net, const double* params, double snr, int64_t n_samples, int k_lo,
+                         int k_hi, double df, const double* psd, double* snr2_scratch, double* xf, hipStream_t s);
+
+}  // namespace fcas

@@ -1,0 +1,66 @@
+// plans.hpp -- FFT plans of the supported segment lengths.
+//
+// N = N1 * N2 with N1 the pass-1 (column) length and N2 the pass-2 (row)
+// length; radix-3 lengths (3 * 2^k) put the factor 3 in the length-768 rows.
+// Work items hold 256 threads for float; the double variants halve the
+// columns / rows per item where the LDS buffer would exceed 64 KiB.
+#pragma once
+
+#include "fitness_tiles.hpp"
+
+namespace fcas {
+
+constexpr int kMaxTiles2 = 128;   // largest N1 / RW over all plans
+
+template <int... R>
+using Rad = Radices<R...>;
+
+// clang-format off
+#define FCAS_PLAN_LIST(X)                                                                          \
+  /*  id     N      N1 E1 rad1          C(f) C(d)  N2  E2 rad2             RW(f) RW(d) */          \
+  X(0,   2048,     32, 8, (8, 4),       64, 64,   64, 8, (8, 8),          32, 32)                  \
+  X(1,   4096,     64, 8, (8, 8),       32, 32,   64, 8, (8, 8),          32, 32)                  \
+  X(2,   8192,     64, 8, (8, 8),       32, 32,  128, 16, (16, 8),        32, 16)                  \
+  X(3,  16384,    128, 16, (16, 8),     32, 16,  128, 16, (16, 8),        32, 16)                  \
+  X(4,  32768,    128, 16, (16, 8),     32, 16,  256, 16, (16, 16),       16, 8)                   \
+  X(5,  65536,    256, 16, (16, 16),    16, 8,   256, 16, (16, 16),       16, 8)                   \
+  X(6, 131072,    256, 16, (16, 16),    16, 8,   512, 8, (8, 8, 8),       4, 4)                    \
+  X(7, 262144,    512, 16, (16, 16, 2), 8, 4,    512, 8, (8, 8, 8),       4, 4)                    \
+  X(8,  24576,     32, 8, (8, 4),       64, 64,  768, 24, (8, 8, 4, 3),   8, 4)                    \
+  X(9,  49152,     64, 8, (8, 8),       32, 32,  768, 24, (8, 8, 4, 3),   8, 4)                    \
+  X(10, 98304,    128, 16, (16, 8),     32, 16,  768, 24, (8, 8, 4, 3),   8, 4)                    \
+  X(11, 196608,   256, 16, (16, 16),    16, 8,   768, 24, (8, 8, 4, 3),   8, 4)
+// clang-format on
+
+#define FCAS_UNPAREN(...) __VA_ARGS__
+
+#define FCAS_DECLARE_PLAN(id, n, n1, e1, r1, cf, cd, n2, e2, r2, rwf, rwd)                   \
+  using PlanF##id = Plan<n1, e1, Rad<FCAS_UNPAREN r1>, cf, n2, e2, Rad<FCAS_UNPAREN r2>, rwf>; \
+  using PlanD##id = Plan<n1, e1, Rad<FCAS_UNPAREN r1>, cd, n2, e2, Rad<FCAS_UNPAREN r2>, rwd>; \
+  static_assert(PlanF##id::N == n && PlanD##id::N == n, "plan length");                    \
+  static_assert(PlanF##id::TILES2 <= kMaxTiles2 && PlanD##id::TILES2 <= kMaxTiles2, "tiles");
+
+FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
+
+constexpr int kNumPlans = 12;
+
+struct PlanInfo {
+  int64_t n;
+  int n1, n2;
+  int tiles1[2], tiles2[2];   // [precision]: 0 float, 1 double
+  int threads1[2], threads2[2];
+};
+
+#define FCAS_PLAN_INFO(id, n, n1, e1, r1, cf, cd, n2, e2, r2, rwf, rwd)                       \
+  {n, n1, n2, {PlanF##id::TILES1, PlanD##id::TILES1}, {PlanF##id::TILES2, PlanD##id::TILES2}, \
+   {PlanF##id::T1, PlanD##id::T1}, {PlanF##id::T2, PlanD##id::T2}},
+
+inline const PlanInfo kPlans[kNumPlans] = {FCAS_PLAN_LIST(FCAS_PLAN_INFO)};
+
+inline int plan_for_length(int64_t n) {
+  for (int i = 0; i < kNumPlans; ++i)
+    if (kPlans[i].n == n) return i;
+  return -1;
+}
+
+}  // namespace fcas

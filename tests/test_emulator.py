@@ -1,0 +1,70 @@
+"""CPU emulation of the HIP fitness path (its tile, stage and reduction
+functions driven thread by thread, built with the host address sanitizer)
+against the FP64 oracle.  This checks the four-step index arithmetic of every
+FFT plan, the prologue and the max reduction on the CPU, before any GPU run."""
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+from oracle import fitness as F
+from tests._cases import Case
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "tests", "emu", "fcas_emu.cpp")
+CSRC = os.path.join(ROOT, "paper_2002_02150_amd", "csrc")
+BIN = os.path.join(ROOT, "tests", "emu", "_build", "fcas_emu")
+
+# plan index -> N, mirrors the plan list of the library
+PLANS = {0: 2048, 1: 4096, 2: 8192, 3: 16384, 4: 32768, 5: 65536, 6: 131072, 7: 262144,
+         8: 24576, 9: 49152, 10: 98304, 11: 196608}
+
+
+@pytest.fixture(scope="module")
+def emu():
+    deps = [SRC] + [os.path.join(CSRC, f) for f in ("fft_core.hpp", "fitness_tiles.hpp", "plans.hpp")]
+    if not os.path.exists(BIN) or os.path.getmtime(BIN) < max(os.path.getmtime(d) for d in deps):
+        os.makedirs(os.path.dirname(BIN), exist_ok=True)
+        subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                        "-I" + CSRC, SRC, "-o", BIN], check=True)
+    return BIN
+
+
+def _run(emu, tmp_path, case, theta, plan, prec):
+    seg = case.seg
+    D = case.net.n_det
+    pre = str(tmp_path / "in")
+    case.net.pos_m.astype(np.float64).tofile(pre + ".pos")
+    case.net.tensor.reshape(D, 9).astype(np.float64).tofile(pre + ".ten")
+    seg.sigma.astype(np.float64).tofile(pre + ".sigma")
+    (case.f_low / seg.freqs).__pow__(1.0 / 3.0).astype(np.float64).tofile(pre + ".b")
+    np.asarray(theta, dtype=np.float64).tofile(pre + ".theta")
+    yt = np.ascontiguousarray(seg.y.T).astype(np.complex64 if prec == 0 else np.complex128)
+    yt.tofile(pre + ".y")
+    out = str(tmp_path / "out")
+    subprocess.run([emu, str(prec), str(plan), str(D), str(seg.k_lo), str(seg.k_hi), repr(seg.df),
+                    repr(case.f_low), pre, out], check=True)
+    r = np.fromfile(out, dtype=np.float64)
+    return r[:-2], r[-2], int(r[-1])
+
+
+@pytest.mark.parametrize("plan,names,prec", [
+    (0, "HL", 0), (1, "HLV", 0), (2, "HL", 0), (3, "HLVK", 0), (5, "HLVK", 0), (6, "HLVK", 0),
+    (8, "HLV", 0), (7, "HLVK", 0), (2, "HLVK", 1), (8, "HL", 1), (4, "L", 0), (9, "HLVK", 0),
+])
+def test_emulated_path_matches_oracle(emu, tmp_path, plan, names, prec):
+    n = PLANS[plan]
+    fs = 1024.0 if n == 2048 else 2048.0
+    case = Case(names, n, fs, snr=12.0, cfg=50, realization=plan)
+    theta = case.theta0 + np.array([0.01, -0.01, 0.02, 0.003])
+    series, bg, bj = _run(emu, tmp_path, case, theta, plan, prec)
+    ref = case.series(theta)
+    tol = 2e-5 if prec == 0 else 1e-10
+    scale = ref.max()
+    assert np.max(np.abs(series - ref)) <= tol * scale
+    j_ref = int(np.argmax(ref))
+    assert bg == pytest.approx(ref[j_ref], rel=20 * tol)
+    assert bj == j_ref or ref[bj] >= (1 - 1e-4) * ref[j_ref]
+    assert series[bj] == bg

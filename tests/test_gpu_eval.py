@@ -1,0 +1,164 @@
+"""GPU parity of fitness_eval_batch against the FP64 oracle, through the C ABI.
+
+Bars: mixed path (FP64 phase, FP32 data / FFT / projection) within 1e-4
+relative in fitness; the FP64 path within 1e-9; argmax within one sample or an
+equally good sample (near-tie rule).  Sizes span several tiles of every
+plan, ragged segment mixes, chunked workspaces and the benchmark's full size.
+"""
+import numpy as np
+import pytest
+import torch
+
+from tests._cases import Case
+from tests._gpu import assert_parity, dev, make_ctx, oracle_eval, require_gpu, thetas_for, upload
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [  # (N, fs, detectors)
+    (2048, 1024.0, "HL"), (4096, 2048.0, "HLV"), (8192, 1024.0, "HL"), (16384, 2048.0, "HLVK"),
+    (32768, 2048.0, "L"), (24576, 2048.0, "HLV"), (49152, 2048.0, "HLVK"),
+]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+@pytest.mark.parametrize("n,fs,names", SMALL, ids=[f"N{n}-{d}" for n, _, d in SMALL])
+def test_eval_matches_oracle(n, fs, names, prec):
+    require_gpu()
+    case = Case(names, n, fs, snr=12.0, cfg=10, realization=n)
+    rng = np.random.default_rng(n + prec)
+    th = thetas_for(case, rng)
+    ctx = make_ctx(case, prec, max_batch=len(th))
+    upload(ctx, 0, case)
+    f, j = ctx.eval(torch.from_numpy(th).to(dev()), torch.zeros(len(th), dtype=torch.int32, device=dev()))
+    f, j = f.cpu().numpy(), j.cpu().numpy()
+    fo, jo = oracle_eval(case, th)
+    assert_parity(case, th, f, j, fo, jo, 1e-4 if prec == 0 else 1e-9)
+    assert np.isnan(th[-3, 0]) and f[-3] == -np.inf and j[-3] == -1
+    ctx.close()
+
+
+@pytest.mark.parametrize("n,names,batch,n_check", [(131072, "HLVK", 320, 6), (8192, "HL", 40, 40),
+                                                   (262144, "HLVK", 16, 3), (196608, "HLVK", 16, 3)],
+                         ids=["N131072-cfg2", "N8192-cfg1", "N262144", "N196608"])
+def test_eval_full_size_sampled(n, names, batch, n_check):
+    """Full benchmark sizes and launch shape; the oracle checks a sample of points."""
+    require_gpu()
+    fs = 1024.0 if n == 8192 else 2048.0
+    case = Case(names, n, fs, snr=10.0, cfg=2, realization=0)
+    rng = np.random.default_rng(7)
+    th = thetas_for(case, rng, n_near=batch // 2, n_uniform=batch - batch // 2, extras=False)
+    ctx = make_ctx(case, 0, max_batch=batch)
+    upload(ctx, 0, case)
+    f, j = ctx.eval(torch.from_numpy(th).to(dev()), torch.zeros(batch, dtype=torch.int32, device=dev()))
+    f, j = f.cpu().numpy(), j.cpu().numpy()
+    idx = np.unique(np.concatenate([[0, batch - 1], rng.choice(batch, n_check, replace=False)]))
+    fo, jo = oracle_eval(case, th[idx])
+    assert_parity(case, th[idx], f[idx], j[idx], fo, jo, 1e-4)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-4), (1, 1e-10)], ids=["mixed", "fp64"])
+def test_noiseless_identity_on_gpu(prec, tol):
+    """Gamma^2 at the true parameters of a noiseless signal equals SNR^2 and the
+    maximum sits on the injected coalescence sample."""
+    require_gpu()
+    case = Case("HLVK", 16384, 2048.0, snr=11.0, noise=False, cfg=11)
+    ctx = make_ctx(case, prec, max_batch=1)
+    upload(ctx, 0, case)
+    f, j = ctx.eval(torch.from_numpy(case.theta0[None, :].copy()).to(dev()),
+                    torch.zeros(1, dtype=torch.int32, device=dev()))
+    assert f.item() == pytest.approx(121.0, rel=tol)
+    assert j.item() == case.inj["tc_sample"]
+    ctx.close()
+
+
+def test_ragged_segments_in_one_call():
+    """Segments of different lengths (different FFT plans) interleaved in one batch."""
+    require_gpu()
+    cases = [Case("HLV", n, 2048.0, snr=12.0, cfg=12, realization=i) for i, n in enumerate((8192, 24576, 16384))]
+    rng = np.random.default_rng(3)
+    ths, segs = [], []
+    for i, c in enumerate(cases):
+        t = thetas_for(c, rng, n_near=4, n_uniform=4, extras=False)
+        ths.append(t)
+        segs.append(np.full(len(t), i, dtype=np.int32))
+    order = rng.permutation(sum(len(t) for t in ths))
+    th = np.concatenate(ths)[order]
+    sg = np.concatenate(segs)[order]
+    ctx = make_ctx(cases[0], 0, max_batch=len(th), max_segments=3, max_samples=24576)
+    for i, c in enumerate(cases):
+        upload(ctx, i, c)
+    f, j = ctx.eval(torch.from_numpy(th).to(dev()), torch.from_numpy(sg).to(dev()))
+    f, j = f.cpu().numpy(), j.cpu().numpy()
+    for i, c in enumerate(cases):
+        m = sg == i
+        fo, jo = oracle_eval(c, th[m])
+        assert_parity(c, th[m], f[m], j[m], fo, jo, 1e-4)
+    ctx.close()
+
+
+def test_chunked_workspace_is_bitwise_identical_and_repeatable():
+    """A workspace of three evaluations forces chunking; results equal the
+    one-chunk run bit for bit, and repeated calls are bitwise identical."""
+    require_gpu()
+    case = Case("HLVK", 16384, 2048.0, snr=12.0, cfg=13)
+    rng = np.random.default_rng(4)
+    th = torch.from_numpy(thetas_for(case, rng)).to(dev())
+    seg = torch.zeros(th.shape[0], dtype=torch.int32, device=dev())
+    big = make_ctx(case, 0, max_batch=th.shape[0])
+    small = make_ctx(case, 0, max_batch=th.shape[0], workspace_bytes=3 * 2 * 16384 * 8)
+    upload(big, 0, case)
+    upload(small, 0, case)
+    f1, j1 = big.eval(th, seg)
+    f2, j2 = small.eval(th, seg)
+    f3, j3 = big.eval(th, seg)
+    assert torch.equal(f1, f2) and torch.equal(j1, j2)
+    assert torch.equal(f1, f3) and torch.equal(j1, j3)
+    big.close()
+    small.close()
+
+
+def test_unregistered_segment_and_batch_limits():
+    require_gpu()
+    from paper_2002_02150_amd import FcasError
+    case = Case("HL", 4096, 2048.0, snr=10.0, cfg=14)
+    ctx = make_ctx(case, 0, max_batch=4, max_segments=2)
+    upload(ctx, 0, case)
+    th = torch.from_numpy(np.tile(case.theta0, (4, 1))).to(dev())
+    seg = torch.tensor([0, 1, 5, -1], dtype=torch.int32, device=dev())
+    f, j = ctx.eval(th, seg)
+    f, j = f.cpu().numpy(), j.cpu().numpy()
+    assert np.isfinite(f[0]) and j[0] >= 0
+    assert np.all(np.isnan(f[1:])) and np.all(j[1:] == -2)
+    assert ctx.device_error() == 1
+    assert ctx.device_error() == 0
+    # empty batch is a no-op; more than max_batch is refused on the host
+    e = torch.empty(0, 4, dtype=torch.float64, device=dev())
+    ctx.eval(e, torch.empty(0, dtype=torch.int32, device=dev()))
+    with pytest.raises(FcasError) as ei:
+        ctx.eval(torch.zeros(5, 4, dtype=torch.float64, device=dev()), torch.zeros(5, dtype=torch.int32, device=dev()))
+    assert ei.value.code == -6
+    with pytest.raises(FcasError):
+        ctx.set_segment(2, torch.zeros(2, 2049, dtype=torch.complex128, device=dev()),
+                        torch.ones(2, 2049, dtype=torch.float64, device=dev()))
+    ctx.close()
+
+
+def test_library_injection_matches_oracle_signal_model():
+    """fcas_inject (the benchmark's signal generator) reproduces the oracle's
+    injection, amplitude normalisation included."""
+    require_gpu()
+    import synth
+    from oracle import signal as S
+    case = Case("HLVK", 16384, 2048.0, snr=None, noise=False, cfg=15)
+    ctx = make_ctx(case, 0, max_batch=1)
+    th0 = np.array([2.1, -0.7, 40.0, 1.3])
+    prm = dict(psi=0.4, phi_c=1.9, cos_iota=-0.3, tc_sample=5000)
+    ref = S.injection(case.n_samples, case.fs, 30.0, 1000.0, case.net.pos_m, case.net.tensor, case.psd, th0,
+                      prm["psi"], prm["phi_c"], prm["cos_iota"], prm["tc_sample"], snr=9.0)
+    xf = torch.zeros(4, case.n_samples // 2 + 1, dtype=torch.complex128, device=dev())
+    psd = torch.from_numpy(np.ascontiguousarray(case.psd)).to(dev())
+    ctx.inject(xf, psd, *th0, prm["psi"], prm["phi_c"], prm["cos_iota"], prm["tc_sample"] / case.fs, 9.0)
+    got = xf.cpu().numpy()
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
+    ctx.close()

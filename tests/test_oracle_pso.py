@@ -60,8 +60,8 @@ def test_ring_neighbourhood_and_pbest():
         r2 = pso.uniforms4(p.seed, 1, i, 0, 3)
         want = (p.c2 * r2) * (x0[expect_lbest[i]] - x0[i])
         assert np.array_equal(st.v[0, i], (0.0 + 0.0) + want), i
-    assert st.pbest_f[0, 3] == np.float32(5.0)
-    assert st.best_f[0] == np.float32(5.0) and st.best_j[0] == 3
+    assert st.pbest_f[0, 3] == 5.0
+    assert st.best_f[0] == 5.0 and st.best_j[0] == 3
 
 
 def test_velocity_clamp_and_let_them_fly():
