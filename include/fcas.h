@@ -134,6 +134,17 @@ int fitness_eval_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const in
 int fitness_grad_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg,
                        double* d_fitness, int32_t* d_argmax, double* d_grad, void* hip_stream);
 
+/* Gradient ascent ("polish") of n points, typically the best particles of a
+ * search: step s computes dGamma^2/dtheta at fixed j* (as fitness_grad_batch),
+ * evaluates the n_trials points theta + step_frac 2^-t w^2 g / |w g|,
+ * t = 0..n_trials-1 (w = widths of the search rectangle, g the gradient) in
+ * one fitness batch, and moves each point to its best trial if that raises
+ * Gamma^2.  d_theta float64 [n][4] is read and updated in place; d_fitness
+ * float64 [n] and d_argmax int32 [n] receive Gamma^2 and j* at the final
+ * points.  Needs n * n_trials <= max_batch, 1 <= n_trials <= 32. */
+int fitness_polish(fcas_ctx* ctx, int32_t n, double* d_theta, const int32_t* d_seg, int32_t n_steps,
+                   double step_frac, int32_t n_trials, double* d_fitness, int32_t* d_argmax, void* hip_stream);
+
 /* lbest particle swarm (Sec. III).  Positions and velocities live in the unit
  * hypercube of the search rectangle, theta = lo + x (hi - lo).  Random numbers
  * are Philox4x32-10 keyed by the seed, counter (iteration, particle, run,
@@ -156,6 +167,7 @@ typedef struct {
   double* best_x;   /* [R][4]    best position of each run */
   double* best_f;   /* [R]       best fitness of each run */
   int32_t* best_j;  /* [R]       argmax sample at the run's best */
+  int32_t* iteration; /* [1]     iterations taken (pso_init sets 0, pso_step adds 1) */
 } fcas_pso_state;
 
 /* Random initial positions / velocities; pbest_f = best_f = -inf.
@@ -163,13 +175,14 @@ typedef struct {
 int pso_init(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s,
              double* d_theta_out, void* hip_stream);
 
-/* One iteration `iter` (0-based) given d_fitness / d_argmax [R*P] of the
- * current positions (from fitness_eval_batch on the points pso_init or the
- * previous pso_step wrote): updates personal, local and run bests, moves the
- * swarm, and writes the next points to d_theta_next float64 [R*P][4]. */
+/* One iteration given d_fitness / d_argmax [R*P] of the current positions
+ * (from fitness_eval_batch on the points pso_init or the previous pso_step
+ * wrote): updates personal, local and run bests, moves the swarm (inertia of
+ * iteration *s->iteration, read on the device, which is then incremented), and
+ * writes the next points to d_theta_next float64 [R*P][4].  Because the
+ * iteration count lives on the device, one captured iteration can be replayed. */
 int pso_step(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s,
-             const double* d_fitness, const int32_t* d_argmax, int32_t iter,
-             double* d_theta_next, void* hip_stream);
+             const double* d_fitness, const int32_t* d_argmax, double* d_theta_next, void* hip_stream);
 
 /* Best of the M independent runs (Sec. III): d_out_f float64 [1] (the
  * coherent search statistic squared), d_out_theta float64 [4], d_out_j int32
@@ -193,6 +206,11 @@ int fcas_inject(fcas_ctx* ctx, int64_t n_samples, const double* params, double s
 /* Synchronises the device and returns the context's device error flags
  * (bit 0: an unregistered segment id was evaluated), then clears them. */
 int fcas_device_error(fcas_ctx* ctx, int32_t* flags_out);
+
+/* Synchronises and returns the number of parameter points evaluated by
+ * this context since its creation (points inside the search rectangle with a
+ * registered segment; points that left the rectangle are not evaluated). */
+int fcas_evaluated(fcas_ctx* ctx, uint64_t* count_out);
 
 /* Enables (1) or disables (0) per-kernel timing with HIP events recorded on
  * the caller's stream around the FFT pass kernels of fitness_eval_batch. */

@@ -26,21 +26,21 @@ struct PassArgs {
 // Pass 1: prologue (template phase, delays, projection) + length-N1 column
 // FFTs + four-step twiddle, for C columns of one evaluation per work item.
 // ---------------------------------------------------------------------------
-template <typename Real, class PL, int L, int E, class Rad, int I, int Ns>
+template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF = false>
 __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf, const cplx<Real>* tw, int t) {
   if constexpr (I < Rad::count) {
     constexpr int R = Rad::value[I];
     constexpr bool LAST = (I == Rad::count - 1);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      stage_butterflies<Real, L, E, R, Ns, LAST>(v[s], buf, tw, t);
+      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[s], buf, tw, t);
       if constexpr (!LAST) {
         __syncthreads();
         stage_gather<Real, L, E>(v[s], buf, t);
         __syncthreads();
       }
     }
-    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R>(v, buf, tw, t);
+    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false>(v, buf, tw, t);
   }
 }
 
@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
     const SegDesc& sg = a.segs[ev.seg];
     cplx<Real> v[2][PL::E1];
     pass1_prologue<Real, PL>(v, ev, sg, a.n_det, tile, c, p);
-    run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1>(v, buf, tw, p);
+    run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf, tw, p);
     cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
     pass1_store<Real, PL>(v, ws, tile, c, p);
   }
@@ -136,9 +136,15 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
 template <typename Real>
 __global__ void k_finalize(const EvalDesc* __restrict__ evals, const SegDesc* __restrict__ segs,
                            const Real* __restrict__ part_g, const int32_t* __restrict__ part_j, int n,
-                           const int32_t* __restrict__ plan_tiles2, double* __restrict__ fitness,
+                           const int32_t* __restrict__ plan_tiles2, const int32_t* __restrict__ counts,
+                           unsigned long long* __restrict__ evaluated, double* __restrict__ fitness,
                            int32_t* __restrict__ argmax) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) {   // running total of points evaluated (inside the rectangle)
+    unsigned long long t = 0;
+    for (int p = 0; p < kNumPlans; ++p) t += (unsigned long long)counts[p];
+    atomicAdd(evaluated, t);
+  }
   if (e >= n) return;
   const EvalDesc& ev = evals[e];
   if (ev.status == 0) {

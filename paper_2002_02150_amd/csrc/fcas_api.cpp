@@ -60,10 +60,16 @@ struct fcas_ctx {
   int32_t* d_part_j = nullptr;
   int32_t* d_plan_tiles2 = nullptr;
   int32_t* d_err = nullptr;
+  unsigned long long* d_evaluated = nullptr;   // running total of points evaluated
   double* d_sigma2 = nullptr;    // [FCAS_MAX_DET] scratch for segment registration
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   GradBuffers grad{};
+  double* d_pol_grad = nullptr;    // [max_batch][4] polish: gradient at the current points
+  double* d_pol_cand = nullptr;    // [max_batch][4] polish trials
+  int32_t* d_pol_seg = nullptr;    // [max_batch]
+  double* d_pol_f = nullptr;       // [max_batch]
+  int32_t* d_pol_j = nullptr;      // [max_batch]
   int plan_refs[kNumPlans] = {0};   // registered segments per plan
   bool timing = false;
   std::vector<TimedPair> t_pass1, t_pass2;
@@ -134,7 +140,8 @@ int free_all(fcas_ctx* c) {
   for (void* p : c->seg_y) if (p) hipFree(p);
   for (double* p : c->seg_b) if (p) hipFree(p);
   void* bufs[] = {c->d_net, c->d_segs, c->d_evals, c->d_lists, c->d_counts, c->d_part_g,
-                  c->d_part_j, c->d_plan_tiles2, c->d_err, c->d_sigma2, c->d_ws};
+                  c->d_part_j, c->d_plan_tiles2, c->d_err, c->d_sigma2, c->d_ws,
+                  c->d_pol_grad, c->d_pol_cand, c->d_pol_seg, c->d_pol_f, c->d_pol_j, c->d_evaluated};
   for (void* p : bufs) if (p) hipFree(p);
   free_grad_buffers(c->grad);
   for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
@@ -216,7 +223,12 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
       (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * kMaxTiles2)) ||
       (rc = dev_alloc(&c->d_plan_tiles2, sizeof(int32_t) * kNumPlans)) ||
       (rc = dev_alloc(&c->d_err, sizeof(int32_t))) || (rc = dev_alloc(&c->d_sigma2, sizeof(double) * FCAS_MAX_DET)) ||
-      (rc = dev_alloc(&c->d_ws, ws)) || (rc = alloc_grad_buffers(c->grad, B, net->n_det))) {
+      (rc = dev_alloc(&c->d_ws, ws)) || (rc = alloc_grad_buffers(c->grad, B, net->n_det)) ||
+      (rc = dev_alloc(&c->d_pol_grad, sizeof(double) * 4 * B)) ||
+      (rc = dev_alloc(&c->d_pol_cand, sizeof(double) * 4 * B)) ||
+      (rc = dev_alloc(&c->d_pol_seg, sizeof(int32_t) * B)) || (rc = dev_alloc(&c->d_pol_f, sizeof(double) * B)) ||
+      (rc = dev_alloc(&c->d_pol_j, sizeof(int32_t) * B)) ||
+      (rc = dev_alloc(&c->d_evaluated, sizeof(unsigned long long)))) {
     std::string msg = g_last_error;
     free_all(c);
     delete c;
@@ -230,6 +242,7 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
           hipSuccess ||
       (e = hipMemcpy(c->d_plan_tiles2, tiles2, sizeof tiles2, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_err, 0, sizeof(int32_t))) != hipSuccess ||
+      (e = hipMemset(c->d_evaluated, 0, sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMemset(c->d_counts, 0, sizeof(int32_t) * kNumPlans)) != hipSuccess) {
     rc = hip_fail(e, "context initialisation");
     free_all(c);
@@ -353,14 +366,22 @@ hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t 
   return e;
 }
 
-// Enqueues set-up, both FFT passes of every plan in use, and finalize.
-int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
-                 int32_t* d_argmax, hipStream_t s) {
+// Enqueues the per-point set-up (descriptors and per-plan work lists).
+int enqueue_setup(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, hipStream_t s) {
   hipError_t e;
   if ((e = launch_zero_i32(ctx->d_counts, kNumPlans, s)) != hipSuccess) return hip_fail(e, "zero counters");
   if ((e = launch_setup(ctx->d_net, ctx->d_segs, d_theta, d_seg, n, ctx->d_evals, ctx->d_lists, ctx->d_counts,
                         ctx->cfg.max_batch, ctx->d_err, s)) != hipSuccess)
     return hip_fail(e, "set-up launch");
+  return FCAS_OK;
+}
+
+// Enqueues set-up, both FFT passes of every plan in use, and finalize.
+int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
+                 int32_t* d_argmax, hipStream_t s) {
+  hipError_t e;
+  int rc = enqueue_setup(ctx, n, d_theta, d_seg, s);
+  if (rc) return rc;
   for (int plan = 0; plan < kNumPlans; ++plan) {
     if (ctx->plan_refs[plan] <= 0) continue;
     const PlanInfo& pi = kPlans[plan];
@@ -387,7 +408,7 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
     }
   }
   if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->d_plan_tiles2,
-                           d_fitness, d_argmax, s)) != hipSuccess)
+                           ctx->d_counts, ctx->d_evaluated, d_fitness, d_argmax, s)) != hipSuccess)
     return hip_fail(e, "finalize launch");
   return FCAS_OK;
 }
@@ -420,6 +441,41 @@ int fitness_grad_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const in
   return FCAS_OK;
 }
 
+int fitness_polish(fcas_ctx* ctx, int32_t n, double* d_theta, const int32_t* d_seg, int32_t n_steps,
+                   double step_frac, int32_t n_trials, double* d_fitness, int32_t* d_argmax, void* hip_stream) {
+  int rc = validate_batch(ctx, n, d_theta, d_seg, d_fitness, d_argmax);
+  if (rc) return rc;
+  if (n_steps < 0 || n_trials < 1 || n_trials > 32) return fail(FCAS_EINVAL, "need n_steps >= 0, 1 <= n_trials <= 32");
+  if (!(step_frac > 0) || !std::isfinite(step_frac)) return fail(FCAS_EINVAL, "step_frac must be positive");
+  if ((int64_t)n * n_trials > ctx->cfg.max_batch)
+    return fail(FCAS_ECAPACITY, "n * n_trials = %lld exceeds max_batch = %d", (long long)n * n_trials,
+                ctx->cfg.max_batch);
+  if (n == 0) return FCAS_OK;
+  hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e;
+  if ((rc = enqueue_eval(ctx, n, d_theta, d_seg, d_fitness, d_argmax, s))) return rc;
+  for (int step = 0; step < n_steps; ++step) {
+    // descriptors of the current points (their maximising samples are already in d_argmax)
+    if (step > 0 && (rc = enqueue_setup(ctx, n, d_theta, d_seg, s))) return rc;
+    if ((e = launch_gradient(ctx->prec, ctx->grad, ctx->d_net, ctx->d_segs, ctx->d_evals, d_theta, d_argmax, n,
+                             ctx->net.n_det, ctx->d_pol_grad, s)) !=
+            hipSuccess ||
+        (e = launch_polish_trials(d_theta, ctx->d_pol_grad, d_seg, ctx->d_net, n, n_trials, step_frac,
+                                  ctx->d_pol_cand, ctx->d_pol_seg, s)) != hipSuccess)
+      return hip_fail(e, "polish launch");
+    const int m = n * n_trials;
+    // the trial batch reuses the evaluation buffers: its outputs go to the polish scratch arrays
+    double* cand_f = ctx->d_pol_f;
+    int32_t* cand_j = ctx->d_pol_j;
+    if ((rc = enqueue_eval(ctx, m, ctx->d_pol_cand, ctx->d_pol_seg, cand_f, cand_j, s))) return rc;
+    if ((e = launch_polish_select(d_theta, d_fitness, d_argmax, ctx->d_pol_cand, cand_f, cand_j, n, n_trials, s)) !=
+        hipSuccess)
+      return hip_fail(e, "polish select launch");
+  }
+  return FCAS_OK;
+}
+
 int fcas_inject(fcas_ctx* ctx, int64_t n_samples, const double* params, double snr, const double* d_psd,
                 double* d_xf, void* hip_stream) {
   if (!ctx || !params || !d_psd || !d_xf) return fail(FCAS_EINVAL, "NULL argument");
@@ -444,6 +500,18 @@ int fcas_device_error(fcas_ctx* ctx, int32_t* flags_out) {
   if ((e = hipMemcpy(flags_out, ctx->d_err, sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess)
     return hip_fail(e, "read error flags");
   if ((e = hipMemset(ctx->d_err, 0, sizeof(int32_t))) != hipSuccess) return hip_fail(e, "clear error flags");
+  return FCAS_OK;
+}
+
+int fcas_evaluated(fcas_ctx* ctx, uint64_t* count_out) {
+  if (!ctx || !count_out) return fail(FCAS_EINVAL, "NULL argument");
+  hipSetDevice(ctx->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  unsigned long long v = 0;
+  if ((e = hipMemcpy(&v, ctx->d_evaluated, sizeof v, hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e, "read evaluation count");
+  *count_out = (uint64_t)v;
   return FCAS_OK;
 }
 
@@ -485,9 +553,9 @@ hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s
 hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_finalize_f32(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
-                               double*, int32_t*, hipStream_t);
+                               const int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 hipError_t launch_finalize_f64(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
-                               double*, int32_t*, hipStream_t);
+                               const int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
   return precision ? launch_pass1_f64(plan, a, grid, s) : launch_pass1_f32(plan, a, grid, s);
@@ -496,10 +564,12 @@ hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hi
   return precision ? launch_pass2_f64(plan, a, grid, s) : launch_pass2_f32(plan, a, grid, s);
 }
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                           const int32_t* part_j, int n, const int32_t* plan_tiles2, double* fitness,
-                           int32_t* argmax, hipStream_t s) {
-  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, plan_tiles2, fitness, argmax, s)
-                   : launch_finalize_f32(evals, segs, part_g, part_j, n, plan_tiles2, fitness, argmax, s);
+                           const int32_t* part_j, int n, const int32_t* plan_tiles2, const int32_t* counts,
+                           unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
+  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, plan_tiles2, counts, evaluated, fitness,
+                                         argmax, s)
+                   : launch_finalize_f32(evals, segs, part_g, part_j, n, plan_tiles2, counts, evaluated, fitness,
+                                         argmax, s);
 }
 }  // namespace fcas
 
@@ -512,7 +582,8 @@ int make_pso(const fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state
   if (p->n_iter < 1) return fail(FCAS_EINVAL, "n_iter must be >= 1");
   const double pr[5] = {p->w0, p->w1, p->c1, p->c2, p->vmax};
   if (!finite_all(pr, 5) || !(p->vmax > 0)) return fail(FCAS_EINVAL, "PSO constants must be finite, vmax > 0");
-  if (!s->x || !s->v || !s->pbest_x || !s->pbest_f || !s->pbest_j || !s->best_x || !s->best_f || !s->best_j)
+  if (!s->x || !s->v || !s->pbest_x || !s->pbest_f || !s->pbest_j || !s->best_x || !s->best_f || !s->best_j ||
+      !s->iteration)
     return fail(FCAS_EINVAL, "NULL swarm state array");
   d->n_runs = p->n_runs;
   d->n_particles = p->n_particles;
@@ -535,6 +606,7 @@ int make_pso(const fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state
   d->best_x = s->best_x;
   d->best_f = s->best_f;
   d->best_j = s->best_j;
+  d->iteration = s->iteration;
   return FCAS_OK;
 }
 
@@ -554,14 +626,13 @@ int pso_init(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, d
 }
 
 int pso_step(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, const double* d_fitness,
-             const int32_t* d_argmax, int32_t iter, double* d_theta_next, void* hip_stream) {
+             const int32_t* d_argmax, double* d_theta_next, void* hip_stream) {
   PsoDev d{};
   int rc = make_pso(ctx, p, s, &d);
   if (rc) return rc;
   if (!d_fitness || !d_argmax || !d_theta_next) return fail(FCAS_EINVAL, "NULL device pointer");
-  if (iter < 0) return fail(FCAS_EINVAL, "iter must be >= 0");
   hipSetDevice(ctx->device);
-  hipError_t e = launch_pso_step(d, d_fitness, d_argmax, iter, d_theta_next, (hipStream_t)hip_stream);
+  hipError_t e = launch_pso_step(d, d_fitness, d_argmax, d_theta_next, (hipStream_t)hip_stream);
   return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_step launch");
 }
 

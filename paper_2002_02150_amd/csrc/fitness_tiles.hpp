@@ -180,22 +180,26 @@ FCAS_HD void project_bin(const EvalDesc& ev, const cplx<Real>* y, const double* 
 // Either leaves the outputs in registers (last stage) or scatters them to the
 // transform's LDS buffer, to be gathered back in natural strided order.
 // ---------------------------------------------------------------------------
-template <typename Real, int L, int E, int R, int Ns, bool LAST>
+template <typename Real, int L, int E, int R, int Ns, bool LAST, bool HALF = false>
 FCAS_HD void stage_butterflies(cplx<Real>* vs, cplx<Real>* buf, const cplx<Real>* tw, int t) {
   constexpr int P = L / E;
   constexpr int B = E / R;
   static_assert(E % R == 0, "radix must divide the elements per thread");
+  static_assert(!HALF || (Ns == 1 && B == 1), "half-zero inputs only in a first stage with one butterfly");
 #pragma unroll
   for (int b = 0; b < B; ++b) {
     const int v = t + b * P;
     cplx<Real> x[R];
 #pragma unroll
-    for (int p = 0; p < R; ++p) x[p] = vs[b + p * B];
+    for (int p = 0; p < (HALF ? R / 2 : R); ++p) x[p] = vs[b + p * B];
     if constexpr (Ns > 1) {
 #pragma unroll
       for (int p = 1; p < R; ++p) x[p] = mul(x[p], tw[stockham_tw(v, Ns, R, p, L)]);
     }
-    dft<R>(x);
+    if constexpr (HALF)
+      dft_half<R>(x);
+    else
+      dft<R>(x);
     if constexpr (LAST) {
 #pragma unroll
       for (int p = 0; p < R; ++p) vs[b + p * B] = x[p];
@@ -233,48 +237,91 @@ struct Plan {
 
 // ---------------------------------------------------------------------------
 // Pass 1, thread (c, p) of column tile `tile`: prologue into registers.
-// Register q holds k1 = p + q P1, i.e. bin k = k1 N2 + k2.
+// Register q holds k1 = p + q P1, i.e. bin k = k1 N2 + k2.  Only positive
+// frequencies are in band (k <= k_hi < N/2), so registers q >= E1/2
+// (k1 >= N1/2) are always zero and are left unset: the first stage reads
+// only the lower half.
+//
+// With e_c(k) = exp(2 pi i Phi_k) (FP64 phase, one sine/cosine per bin) and
+// the delay ramps r_i(k) = exp(2 pi i k dly_i),
+//   W_m(k) = e_c(k) sum_i Q_im y^i_k r_i(k).
+// r_i is exact (FP64-reduced) at the thread's first bin and advanced by the
+// constant factor exp(2 pi i (P1 N2) dly_i) from register to register.
 // ---------------------------------------------------------------------------
 template <typename Real, class PL>
 FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDesc& sg, int n_det,
                             int tile, int c, int p) {
+  constexpr int QH = PL::E1 / 2;
+  constexpr int DK = PL::P1 * PL::N2;
   const int k2 = tile * PL::C + c;
+  const int k0 = p * PL::N2 + k2;
   const cplx<Real>* y = (const cplx<Real>*)sg.y;
+  bool in[QH];
 #pragma unroll
-  for (int q = 0; q < PL::E1; ++q) {
-    const int k1 = p + q * PL::P1;
-    const int k = k1 * PL::N2 + k2;
-    cplx<Real> w0 = mk<Real>(0, 0), w1 = mk<Real>(0, 0);
-    if (k >= sg.k_lo && k <= sg.k_hi) project_bin<Real>(ev, y, sg.b, n_det, k, k - sg.k_lo, w0, w1);
-    v[0][q] = w0;
-    v[1][q] = w1;
+  for (int q = 0; q < QH; ++q) {
+    const int k = k0 + q * DK;
+    in[q] = (k >= sg.k_lo) && (k <= sg.k_hi);
+    v[0][q] = mk<Real>(0, 0);
+    v[1][q] = mk<Real>(0, 0);
+  }
+  for (int i = 0; i < n_det; ++i) {
+    const double ph0 = (double)k0 * ev.dly[i], phs = (double)DK * ev.dly[i];
+    Real s, cc;
+    sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
+    cplx<Real> ramp = mk<Real>(cc, s);
+    sincos_rev((Real)(phs - rint(phs)), &s, &cc);
+    const cplx<Real> step = mk<Real>(cc, s);
+    const Real q0 = Basis<Real>::get(ev, i, 0), q1 = Basis<Real>::get(ev, i, 1);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      if (in[q]) {
+        const int kk = k0 + q * DK - sg.k_lo;
+        const cplx<Real> u = mul(y[(int64_t)kk * n_det + i], ramp);
+        v[0][q] = mk<Real>(v[0][q].x + q0 * u.x, v[0][q].y + q0 * u.y);
+        v[1][q] = mk<Real>(v[1][q].x + q1 * u.x, v[1][q].y + q1 * u.y);
+      }
+      ramp = mul(ramp, step);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    if (in[q]) {
+      const double ph = common_phase(ev.coef, sg.b[k0 + q * DK - sg.k_lo]);
+      Real s, cc;
+      sincos_rev((Real)(ph - rint(ph)), &s, &cc);
+      const cplx<Real> e = mk<Real>(cc, s);
+      v[0][q] = mul(v[0][q], e);
+      v[1][q] = mul(v[1][q], e);
+    }
   }
 }
 
-// Pass 1 epilogue: four-step twiddle w_N^{k2 j1}, store B[m][j1][k2].
+// Pass 1 epilogue: store B[m][j1][k2] (the four-step twiddle is applied when
+// pass 2 loads the rows).
 template <typename Real, class PL>
 FCAS_HD void pass1_store(cplx<Real> (&v)[2][PL::E1], cplx<Real>* slot, int tile, int c, int p) {
   const int k2 = tile * PL::C + c;
 #pragma unroll
   for (int q = 0; q < PL::E1; ++q) {
     const int j1 = p + q * PL::P1;
-    const cplx<Real> t = twiddle<Real>(k2 * j1, (int)PL::N);   // k2 j1 < N: no reduction needed
     const int64_t o = (int64_t)j1 * PL::N2 + k2;
-    slot[o] = mul(v[0][q], t);
-    slot[PL::N + o] = mul(v[1][q], t);
+    slot[o] = v[0][q];
+    slot[PL::N + o] = v[1][q];
   }
 }
 
 // Pass 2 prologue: thread (r, p) of row tile `tile` loads row j1 = tile RW + r,
-// register q holds k2 = p + q P2.
+// register q holds k2 = p + q P2, times the four-step twiddle w_N^{k2 j1}.
 template <typename Real, class PL>
 FCAS_HD void pass2_load(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
   const int j1 = tile * PL::RW + r;
   const int64_t row = (int64_t)j1 * PL::N2;
 #pragma unroll
   for (int q = 0; q < PL::E2; ++q) {
-    v[0][q] = slot[row + p + q * PL::P2];
-    v[1][q] = slot[PL::N + row + p + q * PL::P2];
+    const int k2 = p + q * PL::P2;
+    const cplx<Real> t = twiddle<Real>(k2 * j1, (int)PL::N);   // k2 j1 < N: no reduction needed
+    v[0][q] = mul(slot[row + k2], t);
+    v[1][q] = mul(slot[PL::N + row + k2], t);
   }
 }
 

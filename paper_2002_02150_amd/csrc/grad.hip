@@ -10,15 +10,17 @@
 
 namespace fcas {
 
-// One block per (point, detector): the six sums, FP64 accumulation.
+// Blocks (point, detector, part): each part sums a strided share of the
+// in-band bins into six complex FP64 partial sums; the chain kernel adds the
+// parts in a fixed order (deterministic).
 template <typename Real>
 __global__ void __launch_bounds__(256) k_adjoint_sums(const SegDesc* __restrict__ segs,
                                                       const EvalDesc* __restrict__ evals,
-                                                      const int32_t* __restrict__ argmax, int n_det,
+                                                      const int32_t* __restrict__ argmax, int n_det, int parts,
                                                       double* __restrict__ sums) {
-  const int e = blockIdx.x, i = blockIdx.y;
+  const int e = blockIdx.x, i = blockIdx.y, part = blockIdx.z;
   const EvalDesc& ev = evals[e];
-  double* out = sums + ((int64_t)e * n_det + i) * kAdjSums * 2;
+  double* out = sums + (((int64_t)e * n_det + i) * parts + part) * kAdjSums * 2;
   if (ev.status != 1) {
     if (threadIdx.x < kAdjSums * 2) out[threadIdx.x] = 0.0;
     return;
@@ -29,7 +31,7 @@ __global__ void __launch_bounds__(256) k_adjoint_sums(const SegDesc* __restrict_
   const cplx<Real>* y = (const cplx<Real>*)sg.y;
   double acc[kAdjSums][2];
   for (int m = 0; m < kAdjSums; ++m) acc[m][0] = acc[m][1] = 0.0;
-  for (int k = sg.k_lo + threadIdx.x; k <= sg.k_hi; k += 256) {
+  for (int k = sg.k_lo + part * 256 + threadIdx.x; k <= sg.k_hi; k += 256 * parts) {
     const int kk = k - sg.k_lo;
     const double b = sg.b[kk];
     const double phc = common_phase(ev.coef, b);
@@ -87,7 +89,7 @@ __device__ void coef_derivatives(double tau0, double tau15, double fs, double dc
 // One thread per point: chain rule in FP64.
 __global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restrict__ segs,
                         const EvalDesc* __restrict__ evals, const double* __restrict__ theta,
-                        const double* __restrict__ sums, int n, double* __restrict__ grad) {
+                        const double* __restrict__ sums, int parts, int n, double* __restrict__ grad) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   const NetDesc& net = *netp;
@@ -127,9 +129,17 @@ __global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restr
       dV[q][i][1] = sg.sigma[i] * uc;
     }
   }
+  // add the parts of the six sums in a fixed order
+  double S[kMaxDet * kAdjSums * 2];
+  for (int i = 0; i < D; ++i)
+    for (int m = 0; m < kAdjSums * 2; ++m) {
+      double t = 0.0;
+      for (int part = 0; part < parts; ++part)
+        t += sums[(((int64_t)e * D + i) * parts + part) * kAdjSums * 2 + m];
+      S[i * kAdjSums * 2 + m] = t;
+    }
   // z and the derivative sums
   double zr[kMaxDet], zi[kMaxDet];
-  const double* S = sums + (int64_t)e * D * kAdjSums * 2;
   for (int i = 0; i < D; ++i) {
     zr[i] = S[(i * kAdjSums + 0) * 2];
     zi[i] = S[(i * kAdjSums + 0) * 2 + 1];
@@ -195,10 +205,81 @@ __global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restr
   }
 }
 
+// Polish trials: theta_t = theta + step_frac 2^-t w^2 g / |w g|, t = 0..T-1
+// (w = widths of the search rectangle), same segment as the point.
+__global__ void k_polish_trials(const double* __restrict__ theta, const double* __restrict__ grad,
+                                const int32_t* __restrict__ seg, const NetDesc* __restrict__ netp, int n, int trials,
+                                double step_frac, double* __restrict__ cand, int32_t* __restrict__ cand_seg) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const NetDesc& net = *netp;
+  double w[4], nrm = 0.0;
+  for (int d = 0; d < 4; ++d) {
+    w[d] = net.box_hi[d] - net.box_lo[d];
+    nrm += (w[d] * grad[4 * e + d]) * (w[d] * grad[4 * e + d]);
+  }
+  nrm = sqrt(nrm);
+  double s = step_frac;
+  for (int t = 0; t < trials; ++t) {
+    const int64_t o = (int64_t)e * trials + t;
+    for (int d = 0; d < 4; ++d)
+      cand[4 * o + d] = theta[4 * e + d] + (nrm > 0.0 ? s * w[d] * w[d] * grad[4 * e + d] / nrm : 0.0);
+    cand_seg[o] = seg[e];
+    s *= 0.5;
+  }
+}
+
+// Moves each point to its best trial if that raises the fitness.
+__global__ void k_polish_select(double* __restrict__ theta, double* __restrict__ fitness,
+                                int32_t* __restrict__ argmax, const double* __restrict__ cand,
+                                const double* __restrict__ cand_f, const int32_t* __restrict__ cand_j, int n,
+                                int trials) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  int best = -1;
+  double fb = fitness[e];
+  for (int t = 0; t < trials; ++t) {
+    const double f = cand_f[(int64_t)e * trials + t];
+    if (f > fb) {
+      fb = f;
+      best = t;
+    }
+  }
+  if (best >= 0) {
+    const int64_t o = (int64_t)e * trials + best;
+    for (int d = 0; d < 4; ++d) theta[4 * e + d] = cand[4 * o + d];
+    fitness[e] = fb;
+    argmax[e] = cand_j[o];
+  }
+}
+
+hipError_t launch_polish_trials(const double* theta, const double* grad, const int32_t* seg, const NetDesc* net,
+                                int n, int trials, double step_frac, double* cand, int32_t* cand_seg,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_polish_trials, dim3((n + 63) / 64), dim3(64), 0, s, theta, grad, seg, net, n, trials,
+                     step_frac, cand, cand_seg);
+  return hipGetLastError();
+}
+
+hipError_t launch_polish_select(double* theta, double* fitness, int32_t* argmax, const double* cand,
+                                const double* cand_f, const int32_t* cand_j, int n, int trials, hipStream_t s) {
+  hipLaunchKernelGGL(k_polish_select, dim3((n + 63) / 64), dim3(64), 0, s, theta, fitness, argmax, cand, cand_f,
+                     cand_j, n, trials);
+  return hipGetLastError();
+}
+
+int grad_parts(int n, int n_det) {
+  // enough blocks to cover the chip for small batches, one part for large ones
+  int parts = (kAdjMinBlocks + n * n_det - 1) / (n * n_det);
+  return parts < 1 ? 1 : (parts > kAdjMaxParts ? kAdjMaxParts : parts);
+}
+
 int alloc_grad_buffers(GradBuffers& g, int max_batch, int n_det) {
   g.max_batch = max_batch;
   g.n_det = n_det;
-  const size_t bytes = (size_t)max_batch * n_det * kAdjSums * 2 * sizeof(double);
+  // n * n_det * parts <= n * n_det + kAdjMinBlocks for every n
+  const size_t entries = (size_t)max_batch * n_det + kAdjMinBlocks + kAdjMaxParts;
+  const size_t bytes = entries * kAdjSums * 2 * sizeof(double);
   if (hipMalloc((void**)&g.sums, bytes) != hipSuccess) {
     g.sums = nullptr;
     return -5;
@@ -214,14 +295,15 @@ void free_grad_buffers(GradBuffers& g) {
 hipError_t launch_gradient(int precision, const GradBuffers& g, const NetDesc* net, const SegDesc* segs,
                            const EvalDesc* evals, const double* theta, const int32_t* argmax, int n, int n_det,
                            double* grad, hipStream_t s) {
-  const dim3 grid(n, n_det);
+  const int parts = grad_parts(n, n_det);
+  const dim3 grid(n, n_det, parts);
   if (precision == 0)
-    hipLaunchKernelGGL(k_adjoint_sums<float>, grid, dim3(256), 0, s, segs, evals, argmax, n_det, g.sums);
+    hipLaunchKernelGGL(k_adjoint_sums<float>, grid, dim3(256), 0, s, segs, evals, argmax, n_det, parts, g.sums);
   else
-    hipLaunchKernelGGL(k_adjoint_sums<double>, grid, dim3(256), 0, s, segs, evals, argmax, n_det, g.sums);
+    hipLaunchKernelGGL(k_adjoint_sums<double>, grid, dim3(256), 0, s, segs, evals, argmax, n_det, parts, g.sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chain, dim3((n + 63) / 64), dim3(64), 0, s, net, segs, evals, theta, g.sums, n, grad);
+  hipLaunchKernelGGL(k_chain, dim3((n + 63) / 64), dim3(64), 0, s, net, segs, evals, theta, g.sums, parts, n, grad);
   return hipGetLastError();
 }
 

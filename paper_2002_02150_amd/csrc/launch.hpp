@@ -18,8 +18,8 @@ hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* t
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                           const int32_t* part_j, int n, const int32_t* plan_tiles2, double* fitness,
-                           int32_t* argmax, hipStream_t s);
+                           const int32_t* part_j, int n, const int32_t* plan_tiles2, const int32_t* counts,
+                           unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s);
 
 // segment preparation: sigma_i^2 = 4 df sum_B f^-7/3 / S, y = 4 df x f^-7/6 / (S sigma), b = (f/f*)^-1/3
 hipError_t launch_segment_sigma(const double* psd, int n_det, int64_t half, int k_lo, int k_hi, double df,

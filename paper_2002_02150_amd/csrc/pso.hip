@@ -65,14 +65,16 @@ __global__ void k_pso_init(PsoDev p, double* __restrict__ theta) {
     p.best_f[r] = -INFINITY;
     p.best_j[r] = -1;
     for (int d = 0; d < 4; ++d) p.best_x[4 * r + d] = 0.0;
+    if (r == 0) p.iteration[0] = 0;
   }
 }
 
 __global__ void k_pso_step(PsoDev p, const double* __restrict__ fitness, const int32_t* __restrict__ argmax,
-                           int iter, double* __restrict__ theta) {
+                           double* __restrict__ theta) {
 #pragma clang fp contract(off)
   extern __shared__ double pf[];   // personal-best fitness of the run's particles
   const int r = blockIdx.x, i = threadIdx.x, P = p.n_particles;
+  const int iter = p.iteration[0];
   const int64_t base = (int64_t)r * P;
   if (i < P) {
     const int64_t o = base + i;
@@ -120,6 +122,11 @@ __global__ void k_pso_step(PsoDev p, const double* __restrict__ fitness, const i
   }
 }
 
+// advances the device iteration counter once every run has read it
+__global__ void k_pso_tick(int32_t* iteration) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) iteration[0] += 1;
+}
+
 __global__ void k_pso_best(PsoDev p, double* out_f, double* out_theta, int32_t* out_j, int32_t* out_run) {
 #pragma clang fp contract(off)
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -139,10 +146,13 @@ hipError_t launch_pso_init(const PsoDev& p, double* theta_out, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, int iter,
-                           double* theta_next, hipStream_t s) {
+hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, double* theta_next,
+                           hipStream_t s) {
   hipLaunchKernelGGL(k_pso_step, dim3(p.n_runs), dim3(block_for(p.n_particles)),
-                     sizeof(double) * p.n_particles, s, p, fitness, argmax, iter, theta_next);
+                     sizeof(double) * p.n_particles, s, p, fitness, argmax, theta_next);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pso_tick, dim3(1), dim3(64), 0, s, p.iteration);
   return hipGetLastError();
 }
 

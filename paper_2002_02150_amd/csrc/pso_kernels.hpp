@@ -19,11 +19,12 @@ struct PsoDev {
   double* best_x;
   double* best_f;
   int32_t* best_j;
+  int32_t* iteration;
 };
 
 hipError_t launch_pso_init(const PsoDev& p, double* theta_out, hipStream_t s);
-hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, int iter,
-                           double* theta_next, hipStream_t s);
+hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, double* theta_next,
+                           hipStream_t s);
 hipError_t launch_pso_best(const PsoDev& p, double* out_f, double* out_theta, int32_t* out_j, int32_t* out_run,
                            hipStream_t s);
 

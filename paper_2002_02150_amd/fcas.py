@@ -24,8 +24,8 @@ MAX_DET = 8
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP", -5: "ENOMEM", -6: "ECAPACITY"}
 
 EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_set_segment",
-            "fitness_eval_batch", "fitness_grad_batch", "pso_init", "pso_step", "pso_best",
-            "fcas_inject", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
+            "fitness_eval_batch", "fitness_grad_batch", "fitness_polish", "pso_init", "pso_step", "pso_best",
+            "fcas_inject", "fcas_evaluated", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
 
 
 class FcasError(RuntimeError):
@@ -55,7 +55,8 @@ class _PsoParams(ctypes.Structure):
 
 
 class _PsoState(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_void_p) for n in ("x", "v", "pbest_x", "pbest_f", "pbest_j", "best_x", "best_f", "best_j")]
+    _fields_ = [(n, ctypes.c_void_p) for n in ("x", "v", "pbest_x", "pbest_f", "pbest_j", "best_x", "best_f", "best_j",
+                                               "iteration")]
 
 
 _lib = None
@@ -78,10 +79,12 @@ def library():
         "fcas_set_segment": ([vp, i32, i64, vp, vp, vp], ctypes.c_int),
         "fitness_eval_batch": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "fitness_grad_batch": ([vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "fitness_polish": ([vp, i32, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp], ctypes.c_int),
         "pso_init": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp], ctypes.c_int),
-        "pso_step": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, i32, vp, vp], ctypes.c_int),
+        "pso_step": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, vp, vp], ctypes.c_int),
         "pso_best": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, vp, vp, vp], ctypes.c_int),
         "fcas_inject": ([vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp, vp], ctypes.c_int),
+        "fcas_evaluated": ([vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "fcas_device_error": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
         "fcas_set_timing": ([vp, ctypes.c_int], ctypes.c_int),
         "fcas_read_timing": ([vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], ctypes.c_int),
@@ -223,6 +226,12 @@ class Context:
         _check(library().fcas_device_error(self._h, ctypes.byref(v)))
         return v.value
 
+    def evaluated(self):
+        """Points evaluated by this context so far (synchronises)."""
+        v = ctypes.c_uint64(0)
+        _check(library().fcas_evaluated(self._h, ctypes.byref(v)))
+        return v.value
+
     def set_timing(self, on: bool):
         _check(library().fcas_set_timing(self._h, 1 if on else 0))
 
@@ -265,6 +274,7 @@ class Swarm:
         self.best_x = torch.zeros(R, 4, **f64)
         self.best_f = torch.zeros(R, **f64)
         self.best_j = torch.zeros(R, dtype=torch.int32, device=dev)
+        self.iteration = torch.zeros(1, dtype=torch.int32, device=dev)
         self.theta = torch.zeros(R * P, 4, **f64)
         self.out_f = torch.zeros(1, **f64)
         self.out_theta = torch.zeros(4, **f64)
@@ -272,7 +282,7 @@ class Swarm:
         self.out_run = torch.zeros(1, dtype=torch.int32, device=dev)
         self._p = cfg._c()
         self._s = _PsoState(*[t.data_ptr() for t in (self.x, self.v, self.pbest_x, self.pbest_f, self.pbest_j,
-                                                      self.best_x, self.best_f, self.best_j)])
+                                                      self.best_x, self.best_f, self.best_j, self.iteration)])
 
     @property
     def n(self):
@@ -283,11 +293,12 @@ class Swarm:
                                   _stream(self.ctx.device)))
         return self.theta
 
-    def step(self, fitness, argmax, iteration):
+    def step(self, fitness, argmax):
+        """One iteration; the iteration count is kept on the device."""
         _want(fitness, torch.float64, (self.n,), self.ctx.device, "fitness")
         _want(argmax, torch.int32, (self.n,), self.ctx.device, "argmax")
         _check(library().pso_step(self.ctx._h, ctypes.byref(self._p), ctypes.byref(self._s), _ptr(fitness),
-                                  _ptr(argmax), int(iteration), _ptr(self.theta), _stream(self.ctx.device)))
+                                  _ptr(argmax), _ptr(self.theta), _stream(self.ctx.device)))
         return self.theta
 
     def best(self):
@@ -314,29 +325,12 @@ class FitnessFn(torch.autograd.Function):
         return grad_f[:, None] * g, None, None
 
 
-def polish(fctx: Context, theta, seg, steps=20, lr=1e-3):
-    """Gradient ascent of the fitness from the given points, in coordinates
-    scaled by the search-rectangle width, with backtracking: a step that does
-    not raise Gamma^2 is halved (at most 8 times) and otherwise rejected.
-    Returns the improved points and their fitness."""
-    lo = torch.tensor(fctx.box_lo, dtype=torch.float64, device=fctx.device)
-    w = torch.tensor(fctx.box_hi, dtype=torch.float64, device=fctx.device) - lo
-    theta = theta.clone()
-    f, _, g = fctx.grad(theta, seg)
-    for _ in range(steps):
-        step = lr * w * w * g / torch.clamp(torch.linalg.norm(g * w, dim=1, keepdim=True), min=1e-300)
-        accepted = torch.zeros(theta.shape[0], dtype=torch.bool, device=fctx.device)
-        cand_theta = theta.clone()
-        cand_f = f.clone()
-        scale = 1.0
-        for _ in range(8):
-            trial = theta + scale * step
-            ft, _ = fctx.eval(trial, seg)
-            better = (ft > f) & ~accepted
-            cand_theta[better] = trial[better]
-            cand_f[better] = ft[better]
-            accepted |= better
-            scale *= 0.5
-        theta, f = cand_theta, cand_f
-        f, _, g = fctx.grad(theta, seg)
-    return theta, f
+def polish(fctx: Context, theta, seg, steps=20, step_frac=1e-3, trials=8, fitness=None, argmax=None):
+    """Gradient ascent of Gamma^2 from the given points (fitness_polish): theta
+    is updated in place; returns (theta, fitness, argmax) at the final points."""
+    n = fctx._batch_args(theta, seg)
+    fitness = torch.empty(n, dtype=torch.float64, device=fctx.device) if fitness is None else fitness
+    argmax = torch.empty(n, dtype=torch.int32, device=fctx.device) if argmax is None else argmax
+    _check(library().fitness_polish(fctx._h, n, _ptr(theta), _ptr(seg), int(steps), float(step_frac), int(trials),
+                                    _ptr(fitness), _ptr(argmax), _stream(fctx.device)))
+    return theta, fitness, argmax
