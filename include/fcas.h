@@ -54,6 +54,11 @@ extern "C" {
                          projection and maximum in FP32                           */
 #define FCAS_FP64 1   /* everything in FP64 (the plain reference path)            */
 
+/* launch schedule of the two FFT passes (FCAS_MIXED only; FP64 is always two-pass) */
+#define FCAS_SCHEDULE_FUSED 0     /* one persistent launch per plan, passes pipelined  */
+#define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk
+                                     (the faster one on MI355X: recommended)          */
+
 typedef struct fcas_ctx fcas_ctx;
 
 /* Detector network (Sec. II eq. detresponse).  pos_m: vertex of detector i in
@@ -76,7 +81,7 @@ typedef struct {
   int32_t precision;      /* FCAS_MIXED or FCAS_FP64 */
   int32_t max_batch;      /* largest n accepted by fitness_eval/grad_batch */
   int32_t max_segments;   /* segment ids are 0..max_segments-1 */
-  int32_t reserved;
+  int32_t schedule;       /* FCAS_SCHEDULE_TWO_PASS or FCAS_SCHEDULE_FUSED */
   int64_t max_samples;    /* largest segment length N that will be registered */
   int64_t workspace_bytes;/* FFT workspace; 0 = enough for max_batch evaluations
                              of max_samples (batches beyond it run in chunks) */
@@ -97,6 +102,20 @@ size_t fcas_workspace_bytes(const fcas_ctx* ctx);
 
 /* 1 if a segment of n samples has an FFT plan, else 0 (host only, no device). */
 int fcas_supported_n(int64_t n_samples);
+
+/* FFT plans.  A plan splits N = N1 N2 into N1-point column transforms (pass 1,
+ * E1 elements per thread, `cols` columns per work-group) and N2-point row
+ * transforms (pass 2, E2 elements per thread, `rows` rows per work-group);
+ * several plans may serve one length.  fcas_plan_info reports plan `plan`
+ * (float figures; host only, any output may be NULL). */
+int fcas_plan_count(void);
+int fcas_plan_info(int32_t plan, int64_t* n_samples, int32_t* n1, int32_t* n2, int32_t* e1, int32_t* e2,
+                   int32_t* cols, int32_t* rows);
+
+/* Use plan `plan` for segments of its length registered after this call, with
+ * grid1 / grid2 persistent work-groups for its two passes (0 = default).
+ * This is how the autotuner's choice is applied. */
+int fcas_select_plan(fcas_ctx* ctx, int32_t plan, int32_t grid1, int32_t grid2);
 
 /* Registers (or replaces) segment `seg_id` of n_samples samples per detector
  * (Sec. II.D: the template norms are precomputed and the data over-whitened
@@ -204,7 +223,9 @@ int fcas_inject(fcas_ctx* ctx, int64_t n_samples, const double* params, double s
                 double* d_xf, void* hip_stream);
 
 /* Synchronises the device and returns the context's device error flags
- * (bit 0: an unregistered segment id was evaluated), then clears them. */
+ * (bit 0: an unregistered segment id was evaluated; bit 1: a wait of the fused
+ * schedule exceeded its bound, results of that call are not valid), then
+ * clears them. */
 int fcas_device_error(fcas_ctx* ctx, int32_t* flags_out);
 
 /* Synchronises and returns the number of parameter points evaluated by
@@ -213,12 +234,12 @@ int fcas_device_error(fcas_ctx* ctx, int32_t* flags_out);
 int fcas_evaluated(fcas_ctx* ctx, uint64_t* count_out);
 
 /* Enables (1) or disables (0) per-kernel timing with HIP events recorded on
- * the caller's stream around the FFT pass kernels of fitness_eval_batch. */
+ * the caller's stream around the FFT kernels of fitness_eval_batch. */
 int fcas_set_timing(fcas_ctx* ctx, int enable);
 
 /* Synchronises and returns the summed duration (ms) and launch count of the
- * kernel named `which` ("pass1", "pass2", "setup", "finalize") since timing was
- * enabled; resets the counters. */
+ * FFT kernel named `which` ("pass1", "pass2" of the two-pass schedule, "fused"
+ * of the fused schedule) since timing was enabled; resets the counters. */
 int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t* launches);
 
 /* Message of the last failure on the calling thread ("" if none). */

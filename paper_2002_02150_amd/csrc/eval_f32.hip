@@ -3,9 +3,15 @@
 
 namespace fcas {
 
-#define FCAS_CASE_P1(id, ...)                                                              \
-  case id:                                                                                  \
-    hipLaunchKernelGGL((k_pass1<float, PlanF##id>), dim3(grid), dim3(PlanF##id::T1), 0, s, a); \
+#define FCAS_CASE_P1(id, ...)                                                                   \
+  case id:                                                                                       \
+    switch (a.n_det) {                                                                           \
+      case 1: hipLaunchKernelGGL((k_pass1<float, PlanF##id, 1>), dim3(grid), dim3(PlanF##id::T1), 0, s, a); break; \
+      case 2: hipLaunchKernelGGL((k_pass1<float, PlanF##id, 2>), dim3(grid), dim3(PlanF##id::T1), 0, s, a); break; \
+      case 3: hipLaunchKernelGGL((k_pass1<float, PlanF##id, 3>), dim3(grid), dim3(PlanF##id::T1), 0, s, a); break; \
+      case 4: hipLaunchKernelGGL((k_pass1<float, PlanF##id, 4>), dim3(grid), dim3(PlanF##id::T1), 0, s, a); break; \
+      default: hipLaunchKernelGGL((k_pass1<float, PlanF##id, 0>), dim3(grid), dim3(PlanF##id::T1), 0, s, a); break; \
+    }                                                                                            \
     break;
 #define FCAS_CASE_P2(id, ...)                                                              \
   case id:                                                                                  \
@@ -28,6 +34,36 @@ hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+#define FCAS_CASE_FUSED(id, ...)                                                                \
+  case id:                                                                                       \
+    hipLaunchKernelGGL((k_fused<float, PlanF##id>), dim3(grid), dim3(PlanF##id::T1), 0, s, f);   \
+    break;
+#define FCAS_CASE_OCC(id, ...)                                                                              \
+  case id:                                                                                                   \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_fused<float, PlanF##id>, PlanF##id::T1, 0); \
+    break;
+
+hipError_t launch_fused_f32(int plan, const FusedArgs& f, int grid, hipStream_t s) {
+  switch (plan) {
+    FCAS_PLAN_LIST(FCAS_CASE_FUSED)
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Work-groups of the fused kernel of `plan` that one compute unit holds at once.
+int fused_blocks_per_cu(int plan) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (plan) {
+    FCAS_PLAN_LIST(FCAS_CASE_OCC)
+    default:
+      return 0;
+  }
+  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_finalize_f32(const EvalDesc* evals, const SegDesc* segs, const void* part_g,

@@ -3,9 +3,15 @@
 
 namespace fcas {
 
-#define FCAS_CASE_P1(id, ...)                                                              \
-  case id:                                                                                  \
-    hipLaunchKernelGGL((k_pass1<double, PlanD##id>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); \
+#define FCAS_CASE_P1(id, ...)                                                                   \
+  case id:                                                                                       \
+    switch (a.n_det) {                                                                           \
+      case 1: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 1>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
+      case 2: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 2>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
+      case 3: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 3>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
+      case 4: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 4>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
+      default: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 0>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
+    }                                                                                            \
     break;
 #define FCAS_CASE_P2(id, ...)                                                              \
   case id:                                                                                  \

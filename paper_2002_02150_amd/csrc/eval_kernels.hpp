@@ -44,7 +44,7 @@ __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* bu
   }
 }
 
-template <typename Real, class PL>
+template <typename Real, class PL, int DT>
 __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
   constexpr int LP = lds_padded_len(PL::N1);
   __shared__ cplx<Real> lds[PL::C * LP];
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
     const EvalDesc& ev = a.evals[e];
     const SegDesc& sg = a.segs[ev.seg];
     cplx<Real> v[2][PL::E1];
-    pass1_prologue<Real, PL>(v, ev, sg, a.n_det, tile, c, p);
+    pass1_prologue<Real, PL, DT>(v, ev, sg, a.n_det, tile, c, p);
     run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf, tw, p);
     cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
     pass1_store<Real, PL>(v, ws, tile, c, p);
@@ -170,6 +170,119 @@ __global__ void k_finalize(const EvalDesc* __restrict__ evals, const SegDesc* __
   }
   fitness[e] = (double)g;
   argmax[e] = j;
+}
+
+}  // namespace fcas
+
+namespace fcas {
+
+// ---------------------------------------------------------------------------
+// Fused persistent schedule: both passes of every evaluation of one plan in
+// a single launch.  Work items (TILES1 pass-1 tiles and TILES2 pass-2 tiles per
+// evaluation) form a software pipeline in which pass-1 tiles of evaluation
+// e + L interleave with pass-2 tiles of evaluation e:
+//   [P1(0) .. P1(L-1)] [P1(L) P2(0)] [P1(L+1) P2(1)] ... [P2(cnt-L) .. P2(cnt-1)]
+// Work-group w takes items w, w + G, w + 2G, ... (G <= resident work-groups),
+// so ALU-bound pass-1 tiles and bandwidth-bound pass-2 tiles run side by side
+// and only S = `slots` evaluations occupy the workspace (S > L), small enough
+// to stay in the memory-side cache.  A pass-2 tile waits for its evaluation's
+// pass-1 tiles; a pass-1 tile waits for the pass-2 tiles of the evaluation that
+// last used its slot.  Both are earlier in the sequence, so the wait always
+// ends; each wait is also bounded (on overflow an error flag is set and the
+// item proceeds).
+// ---------------------------------------------------------------------------
+struct FusedArgs {
+  PassArgs p;
+  int32_t* done1;    // [max_batch] pass-1 tiles finished, per list position
+  int32_t* done2;    // [max_batch] pass-2 tiles finished, per list position
+  int32_t* err;      // error flags (bit 1: a wait exceeded its bound)
+  int32_t lag;       // L
+  int32_t slots;     // S
+  int32_t max_spin;  // polls before a wait gives up
+};
+
+__device__ __forceinline__ void wait_count(const int32_t* ctr, int target, int max_spin, int32_t* err) {
+  if (threadIdx.x == 0) {
+    int spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (++spins > max_spin) {
+        __hip_atomic_fetch_or(err, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(4);
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void signal_count(int32_t* ctr) {
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename Real, class PL>
+__global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
+  static_assert(PL::T1 == PL::T2, "the fused schedule needs equal work-item sizes");
+  constexpr int LP1 = lds_padded_len(PL::N1), LP2 = lds_padded_len(PL::N2);
+  constexpr int LDSN = (PL::C * LP1 > PL::RW * LP2) ? PL::C * LP1 : PL::RW * LP2;
+  constexpr int NW = PL::T2 / 64;
+  constexpr int T1 = PL::TILES1, T2 = PL::TILES2, T = T1 + T2;
+  __shared__ cplx<Real> lds[LDSN];
+  __shared__ cplx<Real> tw1[PL::N1];
+  __shared__ cplx<Real> tw2[PL::N2];
+  __shared__ Real red_g[NW];
+  __shared__ int red_j[NW];
+  const PassArgs& a = f.p;
+  const int tid = threadIdx.x;
+  for (int m = tid; m < PL::N1; m += PL::T1) tw1[m] = twiddle<Real>(m, PL::N1);
+  for (int m = tid; m < PL::N2; m += PL::T1) tw2[m] = twiddle<Real>(m, PL::N2);
+  __syncthreads();
+  const int cnt = *a.count;
+  const int L = f.lag < cnt ? f.lag : cnt;
+  const int total = cnt * T;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (int item = blockIdx.x; item < total; item += gridDim.x) {
+    int kind, ep, tile;
+    fused_decode(item, cnt, L, T1, T2, kind, ep, tile);
+    const int slot = ep % f.slots;
+    cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
+    const int e = a.list[ep];
+    if (kind == 1) {
+      if (ep >= f.slots) wait_count(f.done2 + (ep - f.slots), T2, f.max_spin, f.err);
+      const EvalDesc& ev = a.evals[e];
+      const SegDesc& sg = a.segs[ev.seg];
+      const int c = tid % PL::C, p = tid / PL::C;
+      cplx<Real> v[2][PL::E1];
+      pass1_prologue<Real, PL>(v, ev, sg, a.n_det, tile, c, p);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, lds + c * LP1, tw1, p);
+      pass1_store<Real, PL>(v, ws, tile, c, p);
+      signal_count(f.done1 + ep);
+    } else {
+      wait_count(f.done1 + ep, T1, f.max_spin, f.err);
+      const int p = tid % PL::P2, r = tid / PL::P2;
+      cplx<Real> v[2][PL::E2];
+      pass2_load<Real, PL>(v, ws, tile, r, p);
+      run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, lds + r * LP2, tw2, p);
+      Real g;
+      int j;
+      pass2_best<Real, PL>(v, tile, r, p, g, j);
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const Real go = __shfl_xor(g, off, 64);
+        const int jo = __shfl_xor(j, off, 64);
+        if (better(go, jo, g, j)) { g = go; j = jo; }
+      }
+      if (lane == 0) { red_g[wave] = g; red_j[wave] = j; }
+      __syncthreads();
+      if (tid == 0) {
+        for (int w = 1; w < NW; ++w)
+          if (better(red_g[w], red_j[w], g, j)) { g = red_g[w]; j = red_j[w]; }
+        ((Real*)a.part_g)[(int64_t)e * kMaxTiles2 + tile] = g;
+        a.part_j[(int64_t)e * kMaxTiles2 + tile] = j;
+      }
+      signal_count(f.done2 + ep);
+    }
+  }
 }
 
 }  // namespace fcas

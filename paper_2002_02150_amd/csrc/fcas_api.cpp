@@ -19,6 +19,8 @@ using namespace fcas;
 
 namespace {
 
+constexpr int kDefaultGrid = 2048;   // persistent work-groups of a pass launch unless tuned
+
 thread_local std::string g_last_error;
 
 int fail(int code, const char* fmt, ...) {
@@ -71,9 +73,14 @@ struct fcas_ctx {
   double* d_pol_f = nullptr;       // [max_batch]
   int32_t* d_pol_j = nullptr;      // [max_batch]
   int plan_refs[kNumPlans] = {0};   // registered segments per plan
+  int schedule = FCAS_SCHEDULE_FUSED;
+  int n_cu = 0;                     // compute units of the device
+  int fused_cap[kNumPlans] = {0};   // resident work-groups of each fused kernel (0 = not queried)
+  int32_t* d_done = nullptr;        // [kNumPlans][2][max_batch] fused-schedule tile counters
   bool timing = false;
-  std::vector<TimedPair> t_pass1, t_pass2;
-  int grid_cap = 2048;
+  std::vector<TimedPair> t_pass1, t_pass2, t_fused;
+  int grid1[kNumPlans], grid2[kNumPlans];   // persistent grid sizes of the two passes
+  int chosen[kNumPlans];                     // plan used for new segments of each length (by default plan)
 };
 
 namespace {
@@ -118,6 +125,8 @@ int validate_config(const fcas_config* c) {
   if (plan_for_length(c->max_samples) < 0)
     return fail(FCAS_EUNSUPPORTED_N, "max_samples %lld has no FFT plan", (long long)c->max_samples);
   if (c->workspace_bytes < 0) return fail(FCAS_EINVAL, "workspace_bytes must be >= 0");
+  if (c->schedule != FCAS_SCHEDULE_FUSED && c->schedule != FCAS_SCHEDULE_TWO_PASS)
+    return fail(FCAS_EINVAL, "schedule must be FCAS_SCHEDULE_FUSED or FCAS_SCHEDULE_TWO_PASS");
   for (int d = 0; d < 4; ++d) {
     if (!std::isfinite(c->box_lo[d]) || !std::isfinite(c->box_hi[d]) || !(c->box_hi[d] >= c->box_lo[d]))
       return fail(FCAS_EINVAL, "search box coordinate %d must satisfy lo <= hi (finite)", d);
@@ -141,11 +150,13 @@ int free_all(fcas_ctx* c) {
   for (double* p : c->seg_b) if (p) hipFree(p);
   void* bufs[] = {c->d_net, c->d_segs, c->d_evals, c->d_lists, c->d_counts, c->d_part_g,
                   c->d_part_j, c->d_plan_tiles2, c->d_err, c->d_sigma2, c->d_ws,
-                  c->d_pol_grad, c->d_pol_cand, c->d_pol_seg, c->d_pol_f, c->d_pol_j, c->d_evaluated};
+                  c->d_pol_grad, c->d_pol_cand, c->d_pol_seg, c->d_pol_f, c->d_pol_j, c->d_evaluated,
+                  c->d_done};
   for (void* p : bufs) if (p) hipFree(p);
   free_grad_buffers(c->grad);
   for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_pass2) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+  for (auto& t : c->t_fused) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   return FCAS_OK;
 }
 
@@ -166,6 +177,33 @@ extern "C" {
 const char* fcas_last_error(void) { return g_last_error.c_str(); }
 
 int fcas_supported_n(int64_t n_samples) { return plan_for_length(n_samples) >= 0 ? 1 : 0; }
+
+int fcas_plan_count(void) { return kNumPlans; }
+
+int fcas_plan_info(int32_t plan, int64_t* n_samples, int32_t* n1, int32_t* n2, int32_t* e1, int32_t* e2,
+                   int32_t* cols, int32_t* rows) {
+  if (plan < 0 || plan >= kNumPlans) return fail(FCAS_EINVAL, "plan %d out of range [0, %d)", plan, kNumPlans);
+  const PlanInfo& pi = kPlans[plan];
+  if (n_samples) *n_samples = pi.n;
+  if (n1) *n1 = pi.n1;
+  if (n2) *n2 = pi.n2;
+  if (e1) *e1 = pi.e1;
+  if (e2) *e2 = pi.e2;
+  if (cols) *cols = pi.cols[0];
+  if (rows) *rows = pi.rows[0];
+  return FCAS_OK;
+}
+
+int fcas_select_plan(fcas_ctx* ctx, int32_t plan, int32_t grid1, int32_t grid2) {
+  if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
+  if (plan < 0 || plan >= kNumPlans) return fail(FCAS_EINVAL, "plan %d out of range [0, %d)", plan, kNumPlans);
+  if (grid1 < 0 || grid2 < 0 || grid1 > (1 << 20) || grid2 > (1 << 20))
+    return fail(FCAS_EINVAL, "grid sizes must be in [0, 2^20]");
+  ctx->chosen[plan_for_length(kPlans[plan].n)] = plan;
+  ctx->grid1[plan] = grid1 > 0 ? grid1 : kDefaultGrid;
+  ctx->grid2[plan] = grid2 > 0 ? grid2 : kDefaultGrid;
+  return FCAS_OK;
+}
 
 int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fcas_ctx** out) {
   g_last_error.clear();
@@ -192,6 +230,13 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
   c->net = *net;
   c->cfg = *cfg;
   c->prec = cfg->precision == FCAS_FP64 ? 1 : 0;
+  for (int i = 0; i < kNumPlans; ++i) {
+    c->grid1[i] = c->grid2[i] = kDefaultGrid;
+    c->chosen[i] = i;
+  }
+  c->schedule = (c->prec == 0 && cfg->schedule == FCAS_SCHEDULE_FUSED) ? FCAS_SCHEDULE_FUSED : FCAS_SCHEDULE_TWO_PASS;
+  if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
+    c->n_cu = 1;
   c->elt = c->prec ? 16 : 8;
   NetDesc& h = c->h_net;
   h.n_det = net->n_det;
@@ -228,7 +273,8 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
       (rc = dev_alloc(&c->d_pol_cand, sizeof(double) * 4 * B)) ||
       (rc = dev_alloc(&c->d_pol_seg, sizeof(int32_t) * B)) || (rc = dev_alloc(&c->d_pol_f, sizeof(double) * B)) ||
       (rc = dev_alloc(&c->d_pol_j, sizeof(int32_t) * B)) ||
-      (rc = dev_alloc(&c->d_evaluated, sizeof(unsigned long long)))) {
+      (rc = dev_alloc(&c->d_evaluated, sizeof(unsigned long long))) ||
+      (rc = dev_alloc(&c->d_done, sizeof(int32_t) * 2 * (size_t)kNumPlans * B))) {
     std::string msg = g_last_error;
     free_all(c);
     delete c;
@@ -269,8 +315,10 @@ int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples, const dou
   if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
   if (seg_id < 0 || seg_id >= ctx->cfg.max_segments)
     return fail(FCAS_ENOSEG, "segment id %d out of range [0, %d)", seg_id, ctx->cfg.max_segments);
-  const int plan = plan_for_length(n_samples);
-  if (plan < 0) return fail(FCAS_EUNSUPPORTED_N, "segment length %lld has no FFT plan", (long long)n_samples);
+  const int default_plan = plan_for_length(n_samples);
+  if (default_plan < 0)
+    return fail(FCAS_EUNSUPPORTED_N, "segment length %lld has no FFT plan", (long long)n_samples);
+  const int plan = ctx->chosen[default_plan];
   if (n_samples > ctx->cfg.max_samples)
     return fail(FCAS_EINVAL, "segment length %lld exceeds max_samples %lld", (long long)n_samples,
                 (long long)ctx->cfg.max_samples);
@@ -376,18 +424,79 @@ int enqueue_setup(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t
   return FCAS_OK;
 }
 
+PassArgs pass_args(fcas_ctx* ctx, int plan, int cap) {
+  PassArgs a{};
+  a.segs = ctx->d_segs;
+  a.evals = ctx->d_evals;
+  a.list = ctx->d_lists + (size_t)plan * ctx->cfg.max_batch;
+  a.count = ctx->d_counts + plan;
+  a.ws = ctx->d_ws;
+  a.part_g = ctx->d_part_g;
+  a.part_j = ctx->d_part_j;
+  a.n_det = ctx->net.n_det;
+  a.chunk_begin = 0;
+  a.cap = cap;
+  return a;
+}
+
+// One persistent launch of the fused schedule for the points of `plan`.
+int enqueue_fused(fcas_ctx* ctx, int plan, int n, int cap, hipStream_t s) {
+  const PlanInfo& pi = kPlans[plan];
+  if (ctx->fused_cap[plan] == 0) {
+    const int nb = fused_blocks_per_cu(plan);
+    if (nb < 1) return fail(FCAS_EHIP, "fused kernel of plan %d cannot be resident", plan);
+    ctx->fused_cap[plan] = nb * ctx->n_cu;
+  }
+  const int T = pi.tiles1[0] + pi.tiles2[0];
+  const int grid = std::min(ctx->fused_cap[plan], n * T);
+  // pipeline lag: about two rounds of the grid between a tile and its consumer
+  int lag = (2 * grid + T - 1) / T;
+  int slots = 2 * lag + 2;
+  if (slots > cap) {
+    slots = cap;
+    lag = slots - 1;
+  }
+  FusedArgs f{};
+  f.p = pass_args(ctx, plan, cap);
+  f.done1 = ctx->d_done + (size_t)plan * 2 * ctx->cfg.max_batch;
+  f.done2 = f.done1 + ctx->cfg.max_batch;
+  f.err = ctx->d_err;
+  f.lag = lag;
+  f.slots = slots;
+  f.max_spin = 1 << 18;
+  TimedPair tp{};
+  if (ctx->timing) {
+    hipEventCreate(&tp.a);
+    hipEventCreate(&tp.b);
+    hipEventRecord(tp.a, s);
+  }
+  hipError_t e = launch_fused_f32(plan, f, grid, s);
+  if (ctx->timing) {
+    hipEventRecord(tp.b, s);
+    ctx->t_fused.push_back(tp);
+  }
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "fused launch");
+}
+
 // Enqueues set-up, both FFT passes of every plan in use, and finalize.
 int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
                  int32_t* d_argmax, hipStream_t s) {
   hipError_t e;
   int rc = enqueue_setup(ctx, n, d_theta, d_seg, s);
   if (rc) return rc;
+  if (ctx->schedule == FCAS_SCHEDULE_FUSED &&
+      (e = launch_zero_i32(ctx->d_done, 2 * kNumPlans * ctx->cfg.max_batch, s)) != hipSuccess)
+    return hip_fail(e, "zero tile counters");
   for (int plan = 0; plan < kNumPlans; ++plan) {
     if (ctx->plan_refs[plan] <= 0) continue;
     const PlanInfo& pi = kPlans[plan];
     const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
     int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
     if (cap < 1) cap = 1;
+    if (ctx->schedule == FCAS_SCHEDULE_FUSED) {
+      if ((rc = enqueue_fused(ctx, plan, n, cap, s))) return rc;
+      continue;
+    }
     PassArgs a{};
     a.segs = ctx->d_segs;
     a.evals = ctx->d_evals;
@@ -401,8 +510,8 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
     for (int begin = 0; begin < n; begin += cap) {
       a.chunk_begin = begin;
       const int m = std::min(cap, n - begin);
-      const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid_cap);
-      const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid_cap);
+      const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
+      const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
       if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
       if ((e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
     }
@@ -526,7 +635,8 @@ int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t
   std::vector<TimedPair>* rec = nullptr;
   if (!std::strcmp(which, "pass1")) rec = &ctx->t_pass1;
   else if (!std::strcmp(which, "pass2")) rec = &ctx->t_pass2;
-  else return fail(FCAS_EINVAL, "unknown kernel name '%s' (timed: pass1, pass2)", which);
+  else if (!std::strcmp(which, "fused")) rec = &ctx->t_fused;
+  else return fail(FCAS_EINVAL, "unknown kernel name '%s' (timed: pass1, pass2, fused)", which);
   hipSetDevice(ctx->device);
   double tot = 0.0;
   for (auto& t : *rec) {

@@ -248,11 +248,14 @@ struct Plan {
 // r_i is exact (FP64-reduced) at the thread's first bin and advanced by the
 // constant factor exp(2 pi i (P1 N2) dly_i) from register to register.
 // ---------------------------------------------------------------------------
-template <typename Real, class PL>
-FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDesc& sg, int n_det,
+// DT > 0: the detector count is the compile-time constant DT (loops unrolled,
+// every load of the thread issued up front); DT = 0: n_det at run time.
+template <typename Real, class PL, int DT = 0>
+FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDesc& sg, int n_det_rt,
                             int tile, int c, int p) {
   constexpr int QH = PL::E1 / 2;
   constexpr int DK = PL::P1 * PL::N2;
+  const int n_det = DT > 0 ? DT : n_det_rt;
   const int k2 = tile * PL::C + c;
   const int k0 = p * PL::N2 + k2;
   const cplx<Real>* y = (const cplx<Real>*)sg.y;
@@ -264,7 +267,9 @@ FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, cons
     v[0][q] = mk<Real>(0, 0);
     v[1][q] = mk<Real>(0, 0);
   }
-  for (int i = 0; i < n_det; ++i) {
+#pragma unroll
+  for (int i = 0; i < (DT > 0 ? DT : kMaxDet); ++i) {
+    if (DT == 0 && i >= n_det) break;
     const double ph0 = (double)k0 * ev.dly[i], phs = (double)DK * ev.dly[i];
     Real s, cc;
     sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
@@ -340,6 +345,26 @@ FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p
       best = g;
       best_j = j;
     }
+  }
+}
+
+// Work item `item` of the fused schedule (cnt evaluations, lag L, T1 pass-1
+// and T2 pass-2 tiles each): kind 1 / 2 = pass 1 / pass 2, list position ep,
+// tile.  Sequence: [P1(0..L-1)] then rounds [P1(L + r) P2(r)] then [P2(cnt-L..cnt-1)].
+FCAS_HD void fused_decode(int item, int cnt, int L, int T1, int T2, int& kind, int& ep, int& tile) {
+  const int T = T1 + T2;
+  if (item < L * T1) {
+    kind = 1; ep = item / T1; tile = item - ep * T1;
+    return;
+  }
+  const int j = item - L * T1, mid = (cnt - L) * T;
+  if (j < mid) {
+    const int r = j / T, w = j - r * T;
+    if (w < T1) { kind = 1; ep = L + r; tile = w; }
+    else { kind = 2; ep = r; tile = w - T1; }
+  } else {
+    const int k = j - mid;
+    kind = 2; ep = (cnt - L) + k / T2; tile = k - (k / T2) * T2;
   }
 }
 

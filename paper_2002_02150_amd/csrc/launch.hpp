@@ -14,6 +14,10 @@ hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* t
                         int n, EvalDesc* evals, int32_t* lists, int32_t* counts, int list_stride,
                         int32_t* err, hipStream_t s);
 
+// fused persistent schedule (float plans)
+hipError_t launch_fused_f32(int plan, const FusedArgs& f, int grid, hipStream_t s);
+int fused_blocks_per_cu(int plan);
+
 // precision: 0 float, 1 double
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);

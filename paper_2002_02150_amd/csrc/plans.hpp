@@ -29,7 +29,16 @@ using Rad = Radices<R...>;
   X(8,  24576,     32, 8, (8, 4),       64, 64,  768, 24, (8, 8, 4, 3),   8, 4)                    \
   X(9,  49152,     64, 8, (8, 8),       32, 32,  768, 24, (8, 8, 4, 3),   8, 4)                    \
   X(10, 98304,    128, 16, (16, 8),     32, 16,  768, 24, (8, 8, 4, 3),   8, 4)                    \
-  X(11, 196608,   256, 16, (16, 16),    16, 8,   768, 24, (8, 8, 4, 3),   8, 4)
+  X(11, 196608,   256, 16, (16, 16),    16, 8,   768, 24, (8, 8, 4, 3),   8, 4)                    \
+  /* alternatives, picked per device by the autotuner */                                            \
+  X(12, 131072,   128, 16, (16, 8),     32, 16, 1024, 16, (16, 16, 4),    4, 2)                    \
+  X(13, 131072,   256, 16, (16, 16),    16, 8,   512, 16, (16, 16, 2),    8, 4)                    \
+  X(14, 131072,   512, 16, (16, 16, 2), 8, 4,    256, 16, (16, 16),       16, 8)                   \
+  X(15, 131072,   256, 8, (8, 8, 4),    8, 8,    512, 8, (8, 8, 8),       4, 4)                    \
+  X(16, 262144,   256, 16, (16, 16),    16, 8,  1024, 16, (16, 16, 4),    4, 2)                    \
+  X(17,  65536,   128, 16, (16, 8),     32, 16,  512, 8, (8, 8, 8),       4, 4)                    \
+  X(18, 196608,   256, 16, (16, 16),    16, 8,   768, 12, (4, 4, 4, 4, 3), 4, 4)                   \
+  X(19,   8192,   128, 16, (16, 8),     32, 16,   64, 8, (8, 8),          32, 16)
 // clang-format on
 
 #define FCAS_UNPAREN(...) __VA_ARGS__
@@ -42,21 +51,24 @@ using Rad = Radices<R...>;
 
 FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
 
-constexpr int kNumPlans = 12;
+constexpr int kNumPlans = 20;
 
 struct PlanInfo {
   int64_t n;
-  int n1, n2;
-  int tiles1[2], tiles2[2];   // [precision]: 0 float, 1 double
+  int n1, n2, e1, e2;
+  int cols[2], rows[2];       // [precision]: 0 float, 1 double
+  int tiles1[2], tiles2[2];
   int threads1[2], threads2[2];
 };
 
 #define FCAS_PLAN_INFO(id, n, n1, e1, r1, cf, cd, n2, e2, r2, rwf, rwd)                       \
-  {n, n1, n2, {PlanF##id::TILES1, PlanD##id::TILES1}, {PlanF##id::TILES2, PlanD##id::TILES2}, \
+  {n, n1, n2, e1, e2, {cf, cd}, {rwf, rwd},                                                   \
+   {PlanF##id::TILES1, PlanD##id::TILES1}, {PlanF##id::TILES2, PlanD##id::TILES2},           \
    {PlanF##id::T1, PlanD##id::T1}, {PlanF##id::T2, PlanD##id::T2}},
 
 inline const PlanInfo kPlans[kNumPlans] = {FCAS_PLAN_LIST(FCAS_PLAN_INFO)};
 
+// The default plan of a length: the first listed for it.
 inline int plan_for_length(int64_t n) {
   for (int i = 0; i < kNumPlans; ++i)
     if (kPlans[i].n == n) return i;

@@ -19,11 +19,14 @@ LIB_PATH = os.path.join(_HERE, "libfcas.so")
 
 MIXED = 0
 FP64 = 1
+SCHEDULE_FUSED = 0
+SCHEDULE_TWO_PASS = 1
 MAX_DET = 8
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP", -5: "ENOMEM", -6: "ECAPACITY"}
 
-EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_set_segment",
+EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_plan_count",
+            "fcas_plan_info", "fcas_select_plan", "fcas_set_segment",
             "fitness_eval_batch", "fitness_grad_batch", "fitness_polish", "pso_init", "pso_step", "pso_best",
             "fcas_inject", "fcas_evaluated", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
 
@@ -43,7 +46,7 @@ class _Network(ctypes.Structure):
 class _Config(ctypes.Structure):
     _fields_ = [("fs_hz", ctypes.c_double), ("f_low_hz", ctypes.c_double), ("f_high_hz", ctypes.c_double),
                 ("precision", ctypes.c_int32), ("max_batch", ctypes.c_int32), ("max_segments", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("max_samples", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("schedule", ctypes.c_int32), ("max_samples", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("box_lo", ctypes.c_double * 4), ("box_hi", ctypes.c_double * 4)]
 
 
@@ -76,6 +79,9 @@ def library():
         "fcas_destroy": ([vp], ctypes.c_int),
         "fcas_workspace_bytes": ([vp], ctypes.c_size_t),
         "fcas_supported_n": ([i64], ctypes.c_int),
+        "fcas_plan_count": ([], ctypes.c_int),
+        "fcas_plan_info": ([i32] + [ctypes.POINTER(i64)] + [ctypes.POINTER(i32)] * 6, ctypes.c_int),
+        "fcas_select_plan": ([vp, i32, i32, i32], ctypes.c_int),
         "fcas_set_segment": ([vp, i32, i64, vp, vp, vp], ctypes.c_int),
         "fitness_eval_batch": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "fitness_grad_batch": ([vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -107,6 +113,32 @@ def supported_n(n: int) -> bool:
     return bool(library().fcas_supported_n(int(n)))
 
 
+def plans():
+    """[(plan, dict(n, n1, n2, e1, e2, cols, rows))] of every FFT plan."""
+    lib = library()
+    out = []
+    for p in range(lib.fcas_plan_count()):
+        n = ctypes.c_int64()
+        v = [ctypes.c_int32() for _ in range(6)]
+        _check(lib.fcas_plan_info(p, ctypes.byref(n), *[ctypes.byref(x) for x in v]))
+        out.append((p, dict(n=n.value, n1=v[0].value, n2=v[1].value, e1=v[2].value, e2=v[3].value,
+                            cols=v[4].value, rows=v[5].value)))
+    return out
+
+
+TUNING_PATH = os.path.join(_HERE, "tuning.json")
+
+
+def load_tuning(path=TUNING_PATH):
+    """The autotuner's choices {n_samples: {"plan", "grid1", "grid2"}} (empty if none)."""
+    import json
+    if not os.path.exists(path):
+        return {}
+    with open(path) as fh:
+        data = json.load(fh)
+    return {int(k): v for k, v in data.get("choices", {}).items()}
+
+
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -125,7 +157,8 @@ class Context:
     """A library context: network, band, search rectangle, precision, workspace."""
 
     def __init__(self, pos_m, tensor, fs, f_low, f_high, box_lo, box_hi, precision=MIXED, max_batch=320,
-                 max_segments=1, max_samples=131072, workspace_bytes=0, device=0):
+                 max_segments=1, max_samples=131072, workspace_bytes=0, device=0, schedule=SCHEDULE_TWO_PASS,
+                 tuning="default"):
         lib = library()
         net = _Network()
         pos_m = [[float(v) for v in row] for row in pos_m]
@@ -137,7 +170,7 @@ class Context:
                 for b in range(3):
                     net.tensor[i][a][b] = float(tensor[i][a][b])
         cfg = _Config(fs_hz=fs, f_low_hz=f_low, f_high_hz=f_high, precision=precision, max_batch=max_batch,
-                      max_segments=max_segments, reserved=0, max_samples=max_samples,
+                      max_segments=max_segments, schedule=schedule, max_samples=max_samples,
                       workspace_bytes=workspace_bytes)
         for d in range(4):
             cfg.box_lo[d] = float(box_lo[d])
@@ -153,6 +186,14 @@ class Context:
         self.box_lo = [float(v) for v in box_lo]
         self.box_hi = [float(v) for v in box_hi]
         self.seg_samples = {}
+        if tuning is not None:
+            for n, c in (load_tuning() if tuning == "default" else tuning).items():
+                if n <= max_samples and precision == MIXED:
+                    self.select_plan(c["plan"], c.get("grid1", 0), c.get("grid2", 0))
+
+    def select_plan(self, plan, grid1=0, grid2=0):
+        """Plan (and persistent grid sizes) for segments of its length registered from now on."""
+        _check(library().fcas_select_plan(self._h, int(plan), int(grid1), int(grid2)))
 
     @classmethod
     def from_network(cls, net, **kw):

@@ -18,12 +18,13 @@ def dev():
     return torch.device("cuda", 0)
 
 
-def make_ctx(case, precision=0, max_batch=64, max_segments=1, max_samples=None, workspace_bytes=0):
+def make_ctx(case, precision=0, max_batch=64, max_segments=1, max_samples=None, workspace_bytes=0, schedule=1):
     from paper_2002_02150_amd import Context
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
     return Context.from_network(case.net, fs=case.fs, f_low=case.f_low, f_high=case.f_high, box_lo=lo, box_hi=hi,
                                 precision=precision, max_batch=max_batch, max_segments=max_segments,
-                                max_samples=max_samples or case.n_samples, workspace_bytes=workspace_bytes)
+                                max_samples=max_samples or case.n_samples, workspace_bytes=workspace_bytes,
+                                schedule=schedule)
 
 
 def upload(ctx, seg_id, case):

@@ -7,6 +7,7 @@
 // usage: fcas_emu <precision 0|1> <plan> <n_det> <k_lo> <k_hi> <df> <f_star> <in_prefix> <out_file>
 //   inputs  <in_prefix>.{pos,ten,sigma,b,theta} float64, <in_prefix>.y complex64 or complex128 [K][n_det]
 //   output  N float64 Gamma^2_j, then best value, best sample (float64)
+#include <algorithm>
 #include <array>
 #include <cstdio>
 #include <cstdlib>
@@ -154,7 +155,48 @@ static int main_t(int plan, int n_det, int k_lo, int k_hi, double df, double f_s
   return 0;
 }
 
+// Checks the fused-schedule sequence for cnt evaluations with lag L and S
+// slots: every (kind, ep, tile) appears exactly once, a pass-2 tile comes after
+// all pass-1 tiles of its evaluation, and a pass-1 tile comes after all pass-2
+// tiles of the evaluation that used its slot before (ep - S).
+static int check_schedule(int cnt, int L, int S, int T1, int T2) {
+  const int total = cnt * (T1 + T2);
+  std::vector<int> pos1((size_t)cnt * T1, -1), pos2((size_t)cnt * T2, -1);
+  for (int i = 0; i < total; ++i) {
+    int kind, ep, tile;
+    fused_decode(i, cnt, L, T1, T2, kind, ep, tile);
+    if (ep < 0 || ep >= cnt) return 10;
+    if (kind == 1) {
+      if (tile < 0 || tile >= T1 || pos1.at((size_t)ep * T1 + tile) != -1) return 11;
+      pos1[(size_t)ep * T1 + tile] = i;
+    } else if (kind == 2) {
+      if (tile < 0 || tile >= T2 || pos2.at((size_t)ep * T2 + tile) != -1) return 12;
+      pos2[(size_t)ep * T2 + tile] = i;
+    } else {
+      return 13;
+    }
+  }
+  for (int ep = 0; ep < cnt; ++ep) {
+    int last1 = -1, first1 = total, last2 = -1, first2 = total;
+    for (int t = 0; t < T1; ++t) {
+      last1 = std::max(last1, pos1[(size_t)ep * T1 + t]);
+      first1 = std::min(first1, pos1[(size_t)ep * T1 + t]);
+    }
+    for (int t = 0; t < T2; ++t) first2 = std::min(first2, pos2[(size_t)ep * T2 + t]);
+    if (last1 >= first2) return 14;   // pass 2 before its pass 1
+    if (ep >= S) {
+      for (int t = 0; t < T2; ++t) last2 = std::max(last2, pos2[(size_t)(ep - S) * T2 + t]);
+      if (last2 >= first1) return 15;   // slot reused too early
+    }
+  }
+  return 0;
+}
+
 int main(int argc, char** argv) {
+  if (argc == 7 && std::string(argv[1]) == "schedule") {
+    return check_schedule(std::atoi(argv[2]), std::atoi(argv[3]), std::atoi(argv[4]), std::atoi(argv[5]),
+                          std::atoi(argv[6]));
+  }
   if (argc != 10) {
     std::fprintf(stderr, "usage: %s prec plan n_det k_lo k_hi df f_star in_prefix out\n", argv[0]);
     return 1;

@@ -44,6 +44,17 @@ def test_every_declared_symbol_is_exported(lib):
     assert sorted(fcas.EXPORTED) == names
 
 
+def test_plan_table(lib):
+    from paper_2002_02150_amd import fcas
+    ps = fcas.plans()
+    assert len(ps) >= 12
+    for p, d in ps:
+        assert d["n1"] * d["n2"] == d["n"]
+        assert d["n1"] % d["e1"] == 0 and d["n2"] % d["e2"] == 0
+    assert lib.fcas_plan_info(len(ps), None, None, None, None, None, None, None) == -1
+    assert lib.fcas_select_plan(None, 0, 0, 0) == -1
+
+
 def test_supported_lengths(lib):
     from paper_2002_02150_amd import fcas
     for n in (2048, 4096, 8192, 16384, 32768, 65536, 131072, 262144, 24576, 49152, 98304, 196608):
@@ -63,7 +74,7 @@ def _good(prec=0):
             for b in range(3):
                 n.tensor[i][a][b] = net.tensor[i][a][b]
     c = fcas._Config(fs_hz=2048.0, f_low_hz=30.0, f_high_hz=1000.0, precision=prec, max_batch=320,
-                     max_segments=4, reserved=0, max_samples=131072, workspace_bytes=0)
+                     max_segments=4, schedule=0, max_samples=131072, workspace_bytes=0)
     for d in range(4):
         c.box_lo[d] = synth.SEARCH_BOX_30HZ_LO[d]
         c.box_hi[d] = synth.SEARCH_BOX_30HZ_HI[d]
@@ -81,6 +92,7 @@ def _good(prec=0):
     (lambda n, c: c.box_lo.__setitem__(2, -1.0), -1),
     (lambda n, c: c.box_hi.__setitem__(0, -1.0), -1),
     (lambda n, c: n.pos_m[1].__setitem__(0, float("inf")), -1),
+    (lambda n, c: setattr(c, "schedule", 5), -1),
 ])
 def test_create_rejects_bad_arguments_without_device(lib, mutate, code):
     from paper_2002_02150_amd import fcas

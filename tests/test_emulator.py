@@ -19,7 +19,8 @@ BIN = os.path.join(ROOT, "tests", "emu", "_build", "fcas_emu")
 
 # plan index -> N, mirrors the plan list of the library
 PLANS = {0: 2048, 1: 4096, 2: 8192, 3: 16384, 4: 32768, 5: 65536, 6: 131072, 7: 262144,
-         8: 24576, 9: 49152, 10: 98304, 11: 196608}
+         8: 24576, 9: 49152, 10: 98304, 11: 196608,
+         12: 131072, 13: 131072, 14: 131072, 15: 131072, 16: 262144, 17: 65536, 18: 196608, 19: 8192}
 
 
 @pytest.fixture(scope="module")
@@ -53,10 +54,12 @@ def _run(emu, tmp_path, case, theta, plan, prec):
 @pytest.mark.parametrize("plan,names,prec", [
     (0, "HL", 0), (1, "HLV", 0), (2, "HL", 0), (3, "HLVK", 0), (5, "HLVK", 0), (6, "HLVK", 0),
     (8, "HLV", 0), (7, "HLVK", 0), (2, "HLVK", 1), (8, "HL", 1), (4, "L", 0), (9, "HLVK", 0),
+    (12, "HLVK", 0), (13, "HLVK", 0), (14, "HLVK", 0), (15, "HLVK", 0), (16, "HLVK", 0), (17, "HLV", 0),
+    (18, "HLVK", 0), (19, "HL", 0), (12, "HLVK", 1), (18, "HL", 1),
 ])
 def test_emulated_path_matches_oracle(emu, tmp_path, plan, names, prec):
     n = PLANS[plan]
-    fs = 1024.0 if n == 2048 else 2048.0
+    fs = 1024.0 if n in (2048, 8192) else 2048.0
     case = Case(names, n, fs, snr=12.0, cfg=50, realization=plan)
     theta = case.theta0 + np.array([0.01, -0.01, 0.02, 0.003])
     series, bg, bj = _run(emu, tmp_path, case, theta, plan, prec)
@@ -68,3 +71,18 @@ def test_emulated_path_matches_oracle(emu, tmp_path, plan, names, prec):
     assert bg == pytest.approx(ref[j_ref], rel=20 * tol)
     assert bj == j_ref or ref[bj] >= (1 - 1e-4) * ref[j_ref]
     assert series[bj] == bg
+
+
+@pytest.mark.parametrize("T1,T2", [(32, 64), (1, 1), (12, 4), (64, 128), (48, 32)])
+def test_fused_schedule_order(emu, T1, T2):
+    """The fused persistent schedule visits every tile once and every wait
+    targets an earlier item, for the lag / slot choices the library makes
+    (slots = 2 lag + 2, or lag = slots - 1 when the workspace is short)."""
+    cases = []
+    for cnt in (1, 2, 3, 7, 40, 320):
+        for lag in (0, 1, 5, 11, 40):
+            for slots in (lag + 1, 2 * lag + 2):
+                cases.append((cnt, min(lag, cnt), slots))
+    for cnt, lag, slots in cases:
+        r = subprocess.run([emu, "schedule", str(cnt), str(lag), str(slots), str(T1), str(T2)])
+        assert r.returncode == 0, (cnt, lag, slots, r.returncode)

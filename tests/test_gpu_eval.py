@@ -98,15 +98,16 @@ def test_ragged_segments_in_one_call():
 
 
 def test_chunked_workspace_is_bitwise_identical_and_repeatable():
-    """A workspace of three evaluations forces chunking; results equal the
-    one-chunk run bit for bit, and repeated calls are bitwise identical."""
+    """Two-pass schedule: a workspace of three evaluations forces chunking;
+    results equal the one-chunk run bit for bit, and repeated calls are bitwise
+    identical."""
     require_gpu()
     case = Case("HLVK", 16384, 2048.0, snr=12.0, cfg=13)
     rng = np.random.default_rng(4)
     th = torch.from_numpy(thetas_for(case, rng)).to(dev())
     seg = torch.zeros(th.shape[0], dtype=torch.int32, device=dev())
-    big = make_ctx(case, 0, max_batch=th.shape[0])
-    small = make_ctx(case, 0, max_batch=th.shape[0], workspace_bytes=3 * 2 * 16384 * 8)
+    big = make_ctx(case, 0, max_batch=th.shape[0], schedule=1)
+    small = make_ctx(case, 0, max_batch=th.shape[0], workspace_bytes=3 * 2 * 16384 * 8, schedule=1)
     upload(big, 0, case)
     upload(small, 0, case)
     f1, j1 = big.eval(th, seg)
@@ -116,6 +117,41 @@ def test_chunked_workspace_is_bitwise_identical_and_repeatable():
     assert torch.equal(f1, f3) and torch.equal(j1, j3)
     big.close()
     small.close()
+
+
+@pytest.mark.parametrize("ws_slots", [0, 2, 1], ids=["default-workspace", "two-slots", "one-slot"])
+def test_fused_schedule_equals_two_pass(ws_slots):
+    """The fused persistent schedule (pipelined passes in one launch, slot
+    reuse through device-scope release/acquire counters) gives bit-identical
+    results to the two-pass schedule on a ragged batch of several segments,
+    also when the workspace holds only one or two evaluations, and never trips
+    its wait bound."""
+    require_gpu()
+    cases = [Case("HLVK", n, 2048.0, snr=12.0, cfg=16, realization=i) for i, n in enumerate((16384, 24576, 8192))]
+    rng = np.random.default_rng(17)
+    ths, segs = [], []
+    for i, c in enumerate(cases):
+        t = thetas_for(c, rng, n_near=30, n_uniform=30)
+        ths.append(t)
+        segs.append(np.full(len(t), i, dtype=np.int32))
+    order = rng.permutation(sum(len(t) for t in ths))
+    th = torch.from_numpy(np.concatenate(ths)[order]).to(dev())
+    sg = torch.from_numpy(np.concatenate(segs)[order]).to(dev())
+    wsb = ws_slots * 2 * 24576 * 8
+    fused = make_ctx(cases[0], 0, max_batch=th.shape[0], max_segments=3, max_samples=24576, workspace_bytes=wsb,
+                     schedule=0)
+    two = make_ctx(cases[0], 0, max_batch=th.shape[0], max_segments=3, max_samples=24576, schedule=1)
+    for i, c in enumerate(cases):
+        upload(fused, i, c)
+        upload(two, i, c)
+    f1, j1 = fused.eval(th, sg)
+    f2, j2 = two.eval(th, sg)
+    f3, j3 = fused.eval(th, sg)
+    assert fused.device_error() == 0
+    assert torch.equal(f1, f2) and torch.equal(j1, j2)
+    assert torch.equal(f1, f3) and torch.equal(j1, j3)
+    fused.close()
+    two.close()
 
 
 def test_unregistered_segment_and_batch_limits():
