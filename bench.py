@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 N_SAMPLES, FS, F_LOW, F_HIGH = 131072, 2048.0, 30.0, 1000.0
 RUNS, PARTICLES = 8, 40
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("fft_core.hpp", "fitness_tiles.hpp", "plans.hpp", "eval_kernels.hpp", "eval_f32.hip")
+KERNEL_SOURCES = ("fft_core.hpp", "fitness_tiles.hpp", "plans.hpp", "eval_kernels.hpp", "eval_f32.hip", "fcas_api.cpp")
 
 
 def parse():
@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
     ap.add_argument("--schedule", choices=("fused", "two-pass"), default="two-pass")
+    ap.add_argument("--launch-counts", action="store_true",
+                    help="record the points evaluated by each eager launch (adds a sync per step)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, one device-to-device copy of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -197,8 +199,14 @@ def main():
     # timed region 2: K iterations launched eagerly, HIP events around the FFT passes
     ev2 = ctx.evaluated()
     t2 = time.perf_counter()
+    per_launch = []
+    prev = ev2
     for _ in range(a.steps):
         search.iteration(timed=True)
+        if a.launch_counts:      # synchronises every step: only for pairing with counter runs
+            cur = ctx.evaluated()
+            per_launch.append(cur - prev)
+            prev = cur
     torch.cuda.synchronize()
     dt2 = time.perf_counter() - t2
     ev3 = ctx.evaluated()
@@ -228,12 +236,16 @@ def main():
     else:
         name, avg_ms, alg = "k_pass2", avg2, per_launch_p2
     achieved = alg / (avg_ms * 1e-3) / 1e9
+    # measured HBM bytes of this kernel per launch: FETCH_SIZE (x2.0) + WRITE_SIZE
+    # (x1.0) from rocprofv3 counter runs, fitted per evaluated point; valid only
+    # for the kernel sources the counters were taken on
     traffic = None
     tf = os.path.join(ROOT, "profiles", "traffic.json")
     if os.path.exists(tf):
         tr = json.load(open(tf))
         if tr.get("kernel_hash") == kernel_hash() and name in tr.get("kernels", {}):
-            traffic = tr["kernels"][name]["bytes_per_launch"]
+            k = tr["kernels"][name]
+            traffic = k["bytes_per_point"] * pts + k["bytes_fixed"]
     out = {
         "metric": "coherent-fitness evals/s, 4 det x 131072 samples; mixed vs FP64 plain; % HBM BW",
         "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -250,6 +262,7 @@ def main():
         "kernel_ms_per_step": {"k_pass1": avg1, "k_pass2": avg2, "k_fused": avgf},
         "schedule": a.schedule,
         "eager_value": (ev3 - ev2) / dt2, "points_per_launch": pts,
+        "kernel_hash": kernel_hash(),
         "points_per_s": evals / dt, "evaluated_fraction": particle_evals / evals,
         "best": {"fitness": search.pol_f.item(), "argmax": search.pol_j.item(), "iterations": iterations_done},
     }
@@ -261,6 +274,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(xf.cpu().numpy(), psd_d.cpu().numpy(), net,
                                            first_batch.cpu().numpy(), a.cpu_sample)
     ctx.close()
+    if per_launch:
+        out["eager_launch_points"] = per_launch
     if a.calib_copy_mib:
         src = torch.ones(a.calib_copy_mib << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)

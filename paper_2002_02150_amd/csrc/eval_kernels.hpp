@@ -26,7 +26,24 @@ struct PassArgs {
 // Pass 1: prologue (template phase, delays, projection) + length-N1 column
 // FFTs + four-step twiddle, for C columns of one evaluation per work item.
 // ---------------------------------------------------------------------------
-template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF = false>
+// Orders the LDS writes of a stage before the reads of the next.  When every
+// transform is held by threads of one wavefront (WAVE), the lanes of that wave
+// are the only writers and readers of its buffer: waiting for the wave's own
+// LDS operations and keeping the compiler from moving accesses across is
+// enough.  Otherwise the whole work-group synchronises.
+template <bool WAVE>
+__device__ __forceinline__ void lds_exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF = false, bool WAVE = false>
 __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf, const cplx<Real>* tw, int t) {
   if constexpr (I < Rad::count) {
     constexpr int R = Rad::value[I];
@@ -35,12 +52,12 @@ __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* bu
     for (int s = 0; s < 2; ++s) {
       stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[s], buf, tw, t);
       if constexpr (!LAST) {
-        __syncthreads();
+        lds_exchange_sync<WAVE>();
         stage_gather<Real, L, E>(v[s], buf, t);
-        __syncthreads();
+        lds_exchange_sync<WAVE>();
       }
     }
-    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false>(v, buf, tw, t);
+    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE>(v, buf, tw, t);
   }
 }
 
@@ -79,6 +96,8 @@ template <typename Real, class PL>
 __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
   constexpr int LP = lds_padded_len(PL::N2);
   constexpr int NW = PL::T2 / 64;
+  // every row transform lies inside one wavefront: P2 threads, P2 divides 64
+  constexpr bool WAVE = (64 % PL::P2) == 0;
   __shared__ cplx<Real> lds[PL::RW * LP];
   __shared__ cplx<Real> tw[PL::N2];
   __shared__ Real red_g[NW > 0 ? NW : 1];
@@ -92,14 +111,29 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
   const int p = tid % PL::P2, r = tid / PL::P2;
   cplx<Real>* buf = lds + r * LP;
   const int lane = tid & 63, wave = tid >> 6;
-  for (int item = blockIdx.x; item < items; item += gridDim.x) {
+  // software pipeline: the rows of the next item are fetched while this one is transformed
+  cplx<Real> nxt[2][PL::E2];
+  int item = blockIdx.x;
+  if (item < items) {
+    const int slot = item / PL::TILES2;
+    pass2_fetch<Real, PL>(nxt, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, item - slot * PL::TILES2, r, p);
+  }
+  for (; item < items; item += gridDim.x) {
     const int slot = item / PL::TILES2;
     const int tile = item - slot * PL::TILES2;
     const int e = a.list[a.chunk_begin + slot];
-    const cplx<Real>* ws = (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
     cplx<Real> v[2][PL::E2];
-    pass2_load<Real, PL>(v, ws, tile, r, p);
-    run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, buf, tw, p);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int q = 0; q < PL::E2; ++q) v[s][q] = nxt[s][q];
+    const int next = item + gridDim.x;
+    if (next < items) {
+      const int ns = next / PL::TILES2;
+      pass2_fetch<Real, PL>(nxt, (const cplx<Real>*)a.ws + (int64_t)ns * 2 * PL::N, next - ns * PL::TILES2, r, p);
+    }
+    pass2_twiddle<Real, PL>(v, tile, r, p);
+    run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf, tw, p);
     Real g;
     int j;
     pass2_best<Real, PL>(v, tile, r, p, g, j);

@@ -91,6 +91,33 @@ FCAS_HD cplx<R> twiddle(int m, int L) {
   return mk<R>(c, s);
 }
 
+// Streaming (non-temporal) access to the FFT workspace: each element is
+// written once by pass 1 and read once by pass 2, so it should not displace
+// the segment data that every work item re-reads from L2.
+template <typename R>
+FCAS_HD cplx<R> stream_load(const cplx<R>* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  const v2 t = __builtin_nontemporal_load((const v2*)p);
+  return mk<R>(t.x, t.y);
+#else
+  return *p;
+#endif
+}
+
+template <typename R>
+FCAS_HD void stream_store(cplx<R>* p, cplx<R> v) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  typedef R v2 __attribute__((ext_vector_type(2)));
+  v2 t;
+  t.x = v.x;
+  t.y = v.y;
+  __builtin_nontemporal_store(t, (v2*)p);
+#else
+  *p = v;
+#endif
+}
+
 // ---------------------------------------------------------------------------
 // Small inverse DFTs in registers: x[0..R) -> X[0..R), X[j] = sum_p x[p] w_R^{pj}
 // ---------------------------------------------------------------------------

@@ -310,24 +310,42 @@ FCAS_HD void pass1_store(cplx<Real> (&v)[2][PL::E1], cplx<Real>* slot, int tile,
   for (int q = 0; q < PL::E1; ++q) {
     const int j1 = p + q * PL::P1;
     const int64_t o = (int64_t)j1 * PL::N2 + k2;
-    slot[o] = v[0][q];
-    slot[PL::N + o] = v[1][q];
+    stream_store(slot + o, v[0][q]);
+    stream_store(slot + PL::N + o, v[1][q]);
   }
 }
 
-// Pass 2 prologue: thread (r, p) of row tile `tile` loads row j1 = tile RW + r,
-// register q holds k2 = p + q P2, times the four-step twiddle w_N^{k2 j1}.
+// Pass 2 prologue: thread (r, p) of row tile `tile` reads row j1 = tile RW + r,
+// register q holds k2 = p + q P2 (pass2_fetch), then multiplies by the
+// four-step twiddle w_N^{k2 j1} (pass2_twiddle).
 template <typename Real, class PL>
-FCAS_HD void pass2_load(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
+FCAS_HD void pass2_fetch(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
   const int j1 = tile * PL::RW + r;
   const int64_t row = (int64_t)j1 * PL::N2;
 #pragma unroll
   for (int q = 0; q < PL::E2; ++q) {
     const int k2 = p + q * PL::P2;
-    const cplx<Real> t = twiddle<Real>(k2 * j1, (int)PL::N);   // k2 j1 < N: no reduction needed
-    v[0][q] = mul(slot[row + k2], t);
-    v[1][q] = mul(slot[PL::N + row + k2], t);
+    v[0][q] = stream_load(slot + row + k2);
+    v[1][q] = stream_load(slot + PL::N + row + k2);
   }
+}
+
+template <typename Real, class PL>
+FCAS_HD void pass2_twiddle(cplx<Real> (&v)[2][PL::E2], int tile, int r, int p) {
+  const int j1 = tile * PL::RW + r;
+#pragma unroll
+  for (int q = 0; q < PL::E2; ++q) {
+    const int k2 = p + q * PL::P2;
+    const cplx<Real> t = twiddle<Real>(k2 * j1, (int)PL::N);   // k2 j1 < N: no reduction needed
+    v[0][q] = mul(v[0][q], t);
+    v[1][q] = mul(v[1][q], t);
+  }
+}
+
+template <typename Real, class PL>
+FCAS_HD void pass2_load(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
+  pass2_fetch<Real, PL>(v, slot, tile, r, p);
+  pass2_twiddle<Real, PL>(v, tile, r, p);
 }
 
 // Pass 2 epilogue: Gamma^2_j = |a_0|^2 + |a_1|^2 at j = j1 + N1 (p + q P2);

@@ -86,21 +86,32 @@ __device__ void coef_derivatives(double tau0, double tau15, double fs, double dc
   }
 }
 
-// One thread per point: chain rule in FP64.
-__global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restrict__ segs,
-                        const EvalDesc* __restrict__ evals, const double* __restrict__ theta,
-                        const double* __restrict__ sums, int parts, int n, double* __restrict__ grad) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+// One 64-thread block per point: the threads add the parts of the six sums
+// (fixed order, deterministic), then thread 0 applies the chain rule in FP64.
+// Per-point work arrays live in LDS rather than in per-lane scratch.
+__global__ void __launch_bounds__(64) k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restrict__ segs,
+                                              const EvalDesc* __restrict__ evals, const double* __restrict__ theta,
+                                              const double* __restrict__ sums, int parts, int n,
+                                              double* __restrict__ grad) {
+  const int e = blockIdx.x;
   const NetDesc& net = *netp;
   const EvalDesc& ev = evals[e];
   double* g = grad + 4 * (int64_t)e;
   if (ev.status != 1) {
-    g[0] = g[1] = g[2] = g[3] = 0.0;
+    if (threadIdx.x < 4) g[threadIdx.x] = 0.0;
     return;
   }
-  const SegDesc& sg = segs[ev.seg];
   const int D = net.n_det;
+  __shared__ double S[kMaxDet * kAdjSums * 2];
+  for (int m = threadIdx.x; m < D * kAdjSums * 2; m += 64) {
+    const int i = m / (kAdjSums * 2), c = m - i * (kAdjSums * 2);
+    double t = 0.0;
+    for (int part = 0; part < parts; ++part) t += sums[(((int64_t)e * D + i) * parts + part) * kAdjSums * 2 + c];
+    S[m] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const SegDesc& sg = segs[ev.seg];
   const double* th = theta + 4 * (int64_t)e;
   const double alpha = th[0], delta = th[1];
   double dc[2][4];
@@ -113,7 +124,8 @@ __global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restr
   const double dn[2][3] = {{-cd * sa, cd * ca, 0.0}, {-sd * ca, -sd * sa, cd}};
   const double dex[2][3] = {{ca, sa, 0.0}, {0.0, 0.0, 0.0}};
   const double dey[2][3] = {{sd * sa, -sd * ca, 0.0}, {-cd * ca, -cd * sa, -sd}};
-  double dV[2][kMaxDet][2], ddl[2][kMaxDet];
+  __shared__ double dV[2][kMaxDet][2], ddl[2][kMaxDet];
+  __shared__ double zr[kMaxDet], zi[kMaxDet], pz_r[kMaxDet], pz_i[kMaxDet], rr[kMaxDet], ri[kMaxDet];
   for (int i = 0; i < D; ++i) {
     for (int q = 0; q < 2; ++q) {
       const double* r = net.pos[i];
@@ -128,24 +140,10 @@ __global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restr
       dV[q][i][0] = sg.sigma[i] * up;
       dV[q][i][1] = sg.sigma[i] * uc;
     }
-  }
-  // add the parts of the six sums in a fixed order
-  double S[kMaxDet * kAdjSums * 2];
-  for (int i = 0; i < D; ++i)
-    for (int m = 0; m < kAdjSums * 2; ++m) {
-      double t = 0.0;
-      for (int part = 0; part < parts; ++part)
-        t += sums[(((int64_t)e * D + i) * parts + part) * kAdjSums * 2 + m];
-      S[i * kAdjSums * 2 + m] = t;
-    }
-  // z and the derivative sums
-  double zr[kMaxDet], zi[kMaxDet];
-  for (int i = 0; i < D; ++i) {
     zr[i] = S[(i * kAdjSums + 0) * 2];
     zi[i] = S[(i * kAdjSums + 0) * 2 + 1];
   }
   // P z = Q (Q^T z)
-  double pz_r[kMaxDet], pz_i[kMaxDet];
   double c0r = 0, c0i = 0, c1r = 0, c1i = 0;
   for (int i = 0; i < D; ++i) {
     c0r += ev.q[i][0] * zr[i]; c0i += ev.q[i][0] * zi[i];
@@ -157,8 +155,8 @@ __global__ void k_chain(const NetDesc* __restrict__ netp, const SegDesc* __restr
   }
   // w = (V^T V)^-1 V^T z (rank two only), r = z - V w
   double wr[2] = {0, 0}, wi[2] = {0, 0};
-  double rr[kMaxDet] = {0}, ri[kMaxDet] = {0};
   const bool full = (ev.rank == 2);
+  for (int i = 0; i < D; ++i) rr[i] = ri[i] = 0.0;
   if (full) {
     double G00 = 0, G01 = 0, G11 = 0, br0 = 0, bi0 = 0, br1 = 0, bi1 = 0;
     for (int i = 0; i < D; ++i) {
@@ -303,7 +301,7 @@ hipError_t launch_gradient(int precision, const GradBuffers& g, const NetDesc* n
     hipLaunchKernelGGL(k_adjoint_sums<double>, grid, dim3(256), 0, s, segs, evals, argmax, n_det, parts, g.sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_chain, dim3((n + 63) / 64), dim3(64), 0, s, net, segs, evals, theta, g.sums, parts, n, grad);
+  hipLaunchKernelGGL(k_chain, dim3(n), dim3(64), 0, s, net, segs, evals, theta, g.sums, parts, n, grad);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+from oracle import fitness as F
 from tests._cases import Case
 from tests._gpu import assert_parity, dev, make_ctx, oracle_eval, require_gpu, thetas_for, upload
 
@@ -122,10 +123,12 @@ def test_chunked_workspace_is_bitwise_identical_and_repeatable():
 @pytest.mark.parametrize("ws_slots", [0, 2, 1], ids=["default-workspace", "two-slots", "one-slot"])
 def test_fused_schedule_equals_two_pass(ws_slots):
     """The fused persistent schedule (pipelined passes in one launch, slot
-    reuse through device-scope release/acquire counters) gives bit-identical
-    results to the two-pass schedule on a ragged batch of several segments,
-    also when the workspace holds only one or two evaluations, and never trips
-    its wait bound."""
+    reuse through device-scope release/acquire counters) gives the results of
+    the two-pass schedule on a ragged batch of several segments, also when the
+    workspace holds only one or two evaluations, and never trips its wait
+    bound.  The two kernels may contract multiply-adds differently, so values
+    agree to float rounding (2e-6 relative) and samples to the near-tie rule;
+    repeated calls of one schedule are bit-identical."""
     require_gpu()
     cases = [Case("HLVK", n, 2048.0, snr=12.0, cfg=16, realization=i) for i, n in enumerate((16384, 24576, 8192))]
     rng = np.random.default_rng(17)
@@ -148,7 +151,16 @@ def test_fused_schedule_equals_two_pass(ws_slots):
     f2, j2 = two.eval(th, sg)
     f3, j3 = fused.eval(th, sg)
     assert fused.device_error() == 0
-    assert torch.equal(f1, f2) and torch.equal(j1, j2)
+    fin = torch.isfinite(f2)
+    assert torch.equal(torch.isfinite(f1), fin) and torch.equal(j1[~fin], j2[~fin])
+    assert torch.all(torch.abs(f1[fin] - f2[fin]) <= 2e-6 * f2[fin])
+    th_np, sg_np = th.cpu().numpy(), sg.cpu().numpy()
+    f2n, j1n, j2n = f2.cpu().numpy(), j1.cpu().numpy(), j2.cpu().numpy()
+    for k in np.nonzero(fin.cpu().numpy())[0]:
+        if j1n[k] != j2n[k]:
+            c = cases[sg_np[k]]
+            g_at = F.gamma2_at(c.seg, c.net.pos_m, c.net.tensor, th_np[k], int(j1n[k]))
+            assert g_at >= (1 - 1e-4) * f2n[k]
     assert torch.equal(f1, f3) and torch.equal(j1, j3)
     fused.close()
     two.close()
