@@ -43,28 +43,49 @@ __device__ __forceinline__ void lds_exchange_sync() {
   }
 }
 
+// Float transforms exchange both series in one step (LDS buffers buf0 and
+// buf1, two synchronisations per stage); double transforms take turns in buf0,
+// keeping their LDS within 64 KiB per work-group.
+template <typename Real>
+constexpr bool kJointExchange = sizeof(Real) == 4;
+template <typename Real>
+constexpr int kLdsSeries = kJointExchange<Real> ? 2 : 1;
+
+// All stages of both series of one transform.
 template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF = false, bool WAVE = false>
-__device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf, const cplx<Real>* tw, int t) {
+__device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf0, cplx<Real>* buf1,
+                                           const cplx<Real>* tw, int t) {
   if constexpr (I < Rad::count) {
     constexpr int R = Rad::value[I];
     constexpr bool LAST = (I == Rad::count - 1);
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[s], buf, tw, t);
+    if constexpr (kJointExchange<Real>) {
+      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[0], buf0, tw, t);
+      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[1], buf1, tw, t);
       if constexpr (!LAST) {
         lds_exchange_sync<WAVE>();
-        stage_gather<Real, L, E>(v[s], buf, t);
+        stage_gather<Real, L, E>(v[0], buf0, t);
+        stage_gather<Real, L, E>(v[1], buf1, t);
         lds_exchange_sync<WAVE>();
       }
+    } else {
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[s], buf0, tw, t);
+        if constexpr (!LAST) {
+          lds_exchange_sync<WAVE>();
+          stage_gather<Real, L, E>(v[s], buf0, t);
+          lds_exchange_sync<WAVE>();
+        }
+      }
     }
-    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE>(v, buf, tw, t);
+    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE>(v, buf0, buf1, tw, t);
   }
 }
 
 template <typename Real, class PL, int DT>
 __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
   constexpr int LP = lds_padded_len(PL::N1);
-  __shared__ cplx<Real> lds[PL::C * LP];
+  __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::C * LP];
   __shared__ cplx<Real> tw[PL::N1];
   const int tid = threadIdx.x;
   for (int m = tid; m < PL::N1; m += PL::T1) tw[m] = twiddle<Real>(m, PL::N1);
@@ -73,18 +94,48 @@ __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
   cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
   const int items = cnt * PL::TILES1;
   const int c = tid % PL::C, p = tid / PL::C;
-  cplx<Real>* buf = lds + c * LP;
-  for (int item = blockIdx.x; item < items; item += gridDim.x) {
-    const int slot = item / PL::TILES1;
-    const int tile = item - slot * PL::TILES1;
-    const int e = a.list[a.chunk_begin + slot];
-    const EvalDesc& ev = a.evals[e];
-    const SegDesc& sg = a.segs[ev.seg];
-    cplx<Real> v[2][PL::E1];
-    pass1_prologue<Real, PL, DT>(v, ev, sg, a.n_det, tile, c, p);
-    run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf, tw, p);
-    cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
-    pass1_store<Real, PL>(v, ws, tile, c, p);
+  cplx<Real>* buf0 = lds + c * LP;
+  cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::C + c) * LP : buf0;
+  if constexpr (DT > 0) {
+    // software pipeline: the segment data of the next item are fetched while
+    // this one is transformed
+    Pass1Data<Real, PL, DT> nxt;
+    int item = blockIdx.x;
+    if (item < items) {
+      const int slot = item / PL::TILES1;
+      const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
+      pass1_fetch<Real, PL, DT>(nxt, a.segs[ev.seg], item - slot * PL::TILES1, c, p);
+    }
+    for (; item < items; item += gridDim.x) {
+      const int slot = item / PL::TILES1;
+      const int tile = item - slot * PL::TILES1;
+      const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
+      const Pass1Data<Real, PL, DT> cur = nxt;
+      const int next = item + gridDim.x;
+      if (next < items) {
+        const int ns = next / PL::TILES1;
+        const EvalDesc& en = a.evals[a.list[a.chunk_begin + ns]];
+        pass1_fetch<Real, PL, DT>(nxt, a.segs[en.seg], next - ns * PL::TILES1, c, p);
+      }
+      cplx<Real> v[2][PL::E1];
+      pass1_compute<Real, PL, DT>(v, cur, ev);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
+      cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
+      pass1_store<Real, PL>(v, ws, tile, c, p);
+    }
+  } else {
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+      const int slot = item / PL::TILES1;
+      const int tile = item - slot * PL::TILES1;
+      const int e = a.list[a.chunk_begin + slot];
+      const EvalDesc& ev = a.evals[e];
+      const SegDesc& sg = a.segs[ev.seg];
+      cplx<Real> v[2][PL::E1];
+      pass1_prologue<Real, PL, 0>(v, ev, sg, a.n_det, tile, c, p);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
+      cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
+      pass1_store<Real, PL>(v, ws, tile, c, p);
+    }
   }
 }
 
@@ -98,7 +149,7 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
   constexpr int NW = PL::T2 / 64;
   // every row transform lies inside one wavefront: P2 threads, P2 divides 64
   constexpr bool WAVE = (64 % PL::P2) == 0;
-  __shared__ cplx<Real> lds[PL::RW * LP];
+  __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::RW * LP];
   __shared__ cplx<Real> tw[PL::N2];
   __shared__ Real red_g[NW > 0 ? NW : 1];
   __shared__ int red_j[NW > 0 ? NW : 1];
@@ -109,7 +160,8 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
   cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
   const int items = cnt * PL::TILES2;
   const int p = tid % PL::P2, r = tid / PL::P2;
-  cplx<Real>* buf = lds + r * LP;
+  cplx<Real>* buf0 = lds + r * LP;
+  cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::RW + r) * LP : buf0;
   const int lane = tid & 63, wave = tid >> 6;
   // software pipeline: the rows of the next item are fetched while this one is transformed
   cplx<Real> nxt[2][PL::E2];
@@ -133,7 +185,7 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
       pass2_fetch<Real, PL>(nxt, (const cplx<Real>*)a.ws + (int64_t)ns * 2 * PL::N, next - ns * PL::TILES2, r, p);
     }
     pass2_twiddle<Real, PL>(v, tile, r, p);
-    run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf, tw, p);
+    run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf0, buf1, tw, p);
     Real g;
     int j;
     pass2_best<Real, PL>(v, tile, r, p, g, j);
@@ -258,7 +310,7 @@ template <typename Real, class PL>
 __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
   static_assert(PL::T1 == PL::T2, "the fused schedule needs equal work-item sizes");
   constexpr int LP1 = lds_padded_len(PL::N1), LP2 = lds_padded_len(PL::N2);
-  constexpr int LDSN = (PL::C * LP1 > PL::RW * LP2) ? PL::C * LP1 : PL::RW * LP2;
+  constexpr int LDSN = 2 * ((PL::C * LP1 > PL::RW * LP2) ? PL::C * LP1 : PL::RW * LP2);
   constexpr int NW = PL::T2 / 64;
   constexpr int T1 = PL::TILES1, T2 = PL::TILES2, T = T1 + T2;
   __shared__ cplx<Real> lds[LDSN];
@@ -288,7 +340,8 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
       const int c = tid % PL::C, p = tid / PL::C;
       cplx<Real> v[2][PL::E1];
       pass1_prologue<Real, PL>(v, ev, sg, a.n_det, tile, c, p);
-      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, lds + c * LP1, tw1, p);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, lds + c * LP1, lds + (PL::C + c) * LP1,
+                                                                          tw1, p);
       pass1_store<Real, PL>(v, ws, tile, c, p);
       signal_count(f.done1 + ep);
     } else {
@@ -296,7 +349,8 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
       const int p = tid % PL::P2, r = tid / PL::P2;
       cplx<Real> v[2][PL::E2];
       pass2_load<Real, PL>(v, ws, tile, r, p);
-      run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, lds + r * LP2, tw2, p);
+      run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, lds + r * LP2, lds + (PL::RW + r) * LP2, tw2,
+                                                                   p);
       Real g;
       int j;
       pass2_best<Real, PL>(v, tile, r, p, g, j);

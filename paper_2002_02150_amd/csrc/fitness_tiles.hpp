@@ -248,6 +248,78 @@ struct Plan {
 // r_i is exact (FP64-reduced) at the thread's first bin and advanced by the
 // constant factor exp(2 pi i (P1 N2) dly_i) from register to register.
 // ---------------------------------------------------------------------------
+// Segment data one pass-1 thread needs for a work item: y of its in-band
+// registers and detectors, and the basis b of those bins (DT > 0 only).
+template <typename Real, class PL, int DT>
+struct Pass1Data {
+  static constexpr int QH = PL::E1 / 2;
+  cplx<Real> y[DT > 0 ? DT : 1][QH];
+  double b[QH];
+  bool in[QH];
+  int k0;
+};
+
+template <typename Real, class PL, int DT>
+FCAS_HD void pass1_fetch(Pass1Data<Real, PL, DT>& d, const SegDesc& sg, int tile, int c, int p) {
+  constexpr int QH = PL::E1 / 2;
+  constexpr int DK = PL::P1 * PL::N2;
+  static_assert(DT > 0, "prefetch needs a compile-time detector count");
+  const int k2 = tile * PL::C + c;
+  d.k0 = p * PL::N2 + k2;
+  const cplx<Real>* y = (const cplx<Real>*)sg.y;
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    const int k = d.k0 + q * DK;
+    d.in[q] = (k >= sg.k_lo) && (k <= sg.k_hi);
+    const int kk = d.in[q] ? k - sg.k_lo : 0;
+    d.b[q] = sg.b[kk];
+#pragma unroll
+    for (int i = 0; i < DT; ++i) d.y[i][q] = y[(int64_t)kk * DT + i];
+  }
+}
+
+// The prologue arithmetic on prefetched data (same results as pass1_prologue).
+template <typename Real, class PL, int DT>
+FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL, DT>& d, const EvalDesc& ev) {
+  constexpr int QH = PL::E1 / 2;
+  constexpr int DK = PL::P1 * PL::N2;
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    v[0][q] = mk<Real>(0, 0);
+    v[1][q] = mk<Real>(0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < DT; ++i) {
+    const double ph0 = (double)d.k0 * ev.dly[i], phs = (double)DK * ev.dly[i];
+    Real s, cc;
+    sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
+    cplx<Real> ramp = mk<Real>(cc, s);
+    sincos_rev((Real)(phs - rint(phs)), &s, &cc);
+    const cplx<Real> step = mk<Real>(cc, s);
+    const Real q0 = Basis<Real>::get(ev, i, 0), q1 = Basis<Real>::get(ev, i, 1);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      if (d.in[q]) {
+        const cplx<Real> u = mul(d.y[i][q], ramp);
+        v[0][q] = mk<Real>(v[0][q].x + q0 * u.x, v[0][q].y + q0 * u.y);
+        v[1][q] = mk<Real>(v[1][q].x + q1 * u.x, v[1][q].y + q1 * u.y);
+      }
+      ramp = mul(ramp, step);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    if (d.in[q]) {
+      const double ph = common_phase(ev.coef, d.b[q]);
+      Real s, cc;
+      sincos_rev((Real)(ph - rint(ph)), &s, &cc);
+      const cplx<Real> e = mk<Real>(cc, s);
+      v[0][q] = mul(v[0][q], e);
+      v[1][q] = mul(v[1][q], e);
+    }
+  }
+}
+
 // DT > 0: the detector count is the compile-time constant DT (loops unrolled,
 // every load of the thread issued up front); DT = 0: n_det at run time.
 template <typename Real, class PL, int DT = 0>

@@ -58,7 +58,19 @@ static void emu_stages(std::vector<Regs<Real, E>>& regs, std::vector<std::vector
   }
 }
 
-template <typename Real, class PL>
+template <typename Real, class PL, int DT>
+static void prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDesc& sg, int n_det, int tile, int c,
+                     int p) {
+  if constexpr (DT > 0) {
+    Pass1Data<Real, PL, DT> d;
+    pass1_fetch<Real, PL, DT>(d, sg, tile, c, p);
+    pass1_compute<Real, PL, DT>(v, d, ev);
+  } else {
+    pass1_prologue<Real, PL, 0>(v, ev, sg, n_det, tile, c, p);
+  }
+}
+
+template <typename Real, class PL, int DT>
 static void run(const SegDesc& sg, const EvalDesc& ev, int n_det, std::vector<double>& series, double& bg,
                 int& bj) {
   const int64_t N = PL::N;
@@ -71,7 +83,7 @@ static void run(const SegDesc& sg, const EvalDesc& ev, int n_det, std::vector<do
     std::vector<Regs<Real, PL::E1>> regs(PL::T1);
     std::vector<std::vector<cplx<Real>>> bufs(PL::C, std::vector<cplx<Real>>(LP1));
     for (int tid = 0; tid < PL::T1; ++tid)
-      pass1_prologue<Real, PL>(regs[tid].v, ev, sg, n_det, tile, tid % PL::C, tid / PL::C);
+      prologue<Real, PL, DT>(regs[tid].v, ev, sg, n_det, tile, tid % PL::C, tid / PL::C);
     emu_stages<Real, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(
         regs, bufs, tw1, [](size_t t) { return (int)(t % PL::C); }, [](size_t t) { return (int)(t / PL::C); });
     for (int tid = 0; tid < PL::T1; ++tid) pass1_store<Real, PL>(regs[tid].v, ws.data(), tile, tid % PL::C, tid / PL::C);
@@ -138,10 +150,16 @@ static int main_t(int plan, int n_det, int k_lo, int k_hi, double df, double f_s
   std::vector<double> series;
   double bg;
   int bj;
-#define FCAS_EMU_CASE(id, ...)                                                              \
-  case id:                                                                                  \
-    run<Real, std::conditional_t<std::is_same_v<Real, float>, PlanF##id, PlanD##id>>(sg, ev, n_det, series, bg, bj); \
-    break;
+#define FCAS_EMU_CASE(id, ...)                                                                         \
+  case id: {                                                                                           \
+    using PL = std::conditional_t<std::is_same_v<Real, float>, PlanF##id, PlanD##id>;                  \
+    if (n_det == 1) run<Real, PL, 1>(sg, ev, n_det, series, bg, bj);                                   \
+    else if (n_det == 2) run<Real, PL, 2>(sg, ev, n_det, series, bg, bj);                              \
+    else if (n_det == 3) run<Real, PL, 3>(sg, ev, n_det, series, bg, bj);                              \
+    else if (n_det == 4) run<Real, PL, 4>(sg, ev, n_det, series, bg, bj);                              \
+    else run<Real, PL, 0>(sg, ev, n_det, series, bg, bj);                                              \
+    break;                                                                                             \
+  }
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_EMU_CASE)
     default:
