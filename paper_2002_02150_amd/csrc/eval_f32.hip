@@ -70,7 +70,7 @@ hipError_t launch_finalize_f32(const EvalDesc* evals, const SegDesc* segs, const
                                   const int32_t* part_j, int n, const int32_t* plan_tiles2, const int32_t* counts,
                                   unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize<float>, dim3((n + 127) / 128), dim3(128), 0, s, evals, segs,
+  hipLaunchKernelGGL(k_finalize<float>, dim3((n + 3) / 4), dim3(256), 0, s, evals, segs,
                      (const float*)part_g, part_j, n, plan_tiles2, counts, evaluated, fitness, argmax);
   return hipGetLastError();
 }

@@ -217,36 +217,37 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Finalize: one thread per point, maximum over its pass-2 partials.
+// Finalize: one wavefront per point reduces its pass-2 partials.
 // ---------------------------------------------------------------------------
 template <typename Real>
-__global__ void k_finalize(const EvalDesc* __restrict__ evals, const SegDesc* __restrict__ segs,
-                           const Real* __restrict__ part_g, const int32_t* __restrict__ part_j, int n,
-                           const int32_t* __restrict__ plan_tiles2, const int32_t* __restrict__ counts,
-                           unsigned long long* __restrict__ evaluated, double* __restrict__ fitness,
-                           int32_t* __restrict__ argmax) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e == 0) {   // running total of points evaluated (inside the rectangle)
+__global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ evals,
+                                                  const SegDesc* __restrict__ segs, const Real* __restrict__ part_g,
+                                                  const int32_t* __restrict__ part_j, int n,
+                                                  const int32_t* __restrict__ plan_tiles2,
+                                                  const int32_t* __restrict__ counts,
+                                                  unsigned long long* __restrict__ evaluated,
+                                                  double* __restrict__ fitness, int32_t* __restrict__ argmax) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {   // running total of points evaluated (inside the rectangle)
     unsigned long long t = 0;
     for (int p = 0; p < kNumPlans; ++p) t += (unsigned long long)counts[p];
     atomicAdd(evaluated, t);
   }
   if (e >= n) return;
   const EvalDesc& ev = evals[e];
-  if (ev.status == 0) {
-    fitness[e] = -INFINITY;
-    argmax[e] = -1;
-    return;
-  }
-  if (ev.status != 1) {
-    fitness[e] = NAN;
-    argmax[e] = -2;
+  const int status = ev.status;
+  if (status != 1) {
+    if (lane == 0) {
+      fitness[e] = status == 0 ? -INFINITY : NAN;
+      argmax[e] = status == 0 ? -1 : -2;
+    }
     return;
   }
   const int nt = plan_tiles2[ev.plan];
-  Real g = part_g[(int64_t)e * kMaxTiles2];
-  int j = part_j[(int64_t)e * kMaxTiles2];
-  for (int t = 1; t < nt; ++t) {
+  Real g = (Real)-1;
+  int j = 0x7fffffff;
+  for (int t = lane; t < nt; t += 64) {
     const Real go = part_g[(int64_t)e * kMaxTiles2 + t];
     const int jo = part_j[(int64_t)e * kMaxTiles2 + t];
     if (better(go, jo, g, j)) {
@@ -254,8 +255,19 @@ __global__ void k_finalize(const EvalDesc* __restrict__ evals, const SegDesc* __
       j = jo;
     }
   }
-  fitness[e] = (double)g;
-  argmax[e] = j;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const Real go = __shfl_xor(g, off, 64);
+    const int jo = __shfl_xor(j, off, 64);
+    if (better(go, jo, g, j)) {
+      g = go;
+      j = jo;
+    }
+  }
+  if (lane == 0) {
+    fitness[e] = (double)g;
+    argmax[e] = j;
+  }
 }
 
 }  // namespace fcas
