@@ -129,6 +129,14 @@ int fcas_select_plan(fcas_ctx* ctx, int32_t plan, int32_t grid1, int32_t grid2);
 int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples,
                      const double* d_xf, const double* d_psd, void* hip_stream);
 
+/* Restricts the maximisation over the coalescence time (Sec. II.C) for
+ * segment seg_id to samples j_lo <= j < j_hi (default: all N samples, right
+ * for cyclic data).  For a segment cut from a longer stream, searching only its
+ * central part keeps the matched filter away from the wrap-around at the
+ * edges, and overlapping segments cover every coalescence time once.
+ * Synchronous; not capturable; applies to later evaluations. */
+int fcas_set_segment_range(fcas_ctx* ctx, int32_t seg_id, int64_t j_lo, int64_t j_hi);
+
 /* Coherent fitness of n parameter points (Sec. II.C eqs. FCASdetStat,
  * gammaSqd; Sec. II.D).  For each point:
  *   Gamma^2 = max_j max_{A_1..A_4} 2 lambda(theta, A, t_c = j / fs),

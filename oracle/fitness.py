@@ -272,10 +272,11 @@ def in_box(theta, box_lo, box_hi):
     return bool(np.all(np.isfinite(t)) and np.all(t >= box_lo) and np.all(t <= box_hi))
 
 
-def fitness(seg: Segment, pos_m, tensors, theta, box_lo=None, box_hi=None):
+def fitness(seg: Segment, pos_m, tensors, theta, box_lo=None, box_hi=None, j_range=None):
     """Coherent fitness Gamma^2(theta) = max_j Gamma^2_j and the maximising
     sample j* (smallest j among equal maxima).  j*/fs is the coalescence time at
-    the Earth's centre, modulo the segment length.
+    the Earth's centre, modulo the segment length.  j_range = (j_lo, j_hi)
+    restricts the maximum to j_lo <= j < j_hi.
 
     Points outside the search rectangle (or non-finite) get (-inf, -1): the
     particle is allowed to leave the rectangle but is not evaluated there.
@@ -283,15 +284,16 @@ def fitness(seg: Segment, pos_m, tensors, theta, box_lo=None, box_hi=None):
     if box_lo is not None and not in_box(theta, box_lo, box_hi):
         return -math.inf, -1
     g = gamma2_series(seg, pos_m, tensors, theta)
-    j = int(np.argmax(g))
+    lo, hi = (0, len(g)) if j_range is None else j_range
+    j = lo + int(np.argmax(g[lo:hi]))
     return float(g[j]), j
 
 
-def fitness_batch(seg, pos_m, tensors, thetas, box_lo=None, box_hi=None):
+def fitness_batch(seg, pos_m, tensors, thetas, box_lo=None, box_hi=None, j_range=None):
     out_f = np.empty(len(thetas))
     out_j = np.empty(len(thetas), dtype=np.int64)
     for n, th in enumerate(thetas):
-        out_f[n], out_j[n] = fitness(seg, pos_m, tensors, th, box_lo, box_hi)
+        out_f[n], out_j[n] = fitness(seg, pos_m, tensors, th, box_lo, box_hi, j_range)
     return out_f, out_j
 
 

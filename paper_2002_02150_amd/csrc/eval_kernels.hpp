@@ -186,9 +186,10 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
     }
     pass2_twiddle<Real, PL>(v, tile, r, p);
     run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf0, buf1, tw, p);
+    const SegDesc& sg = a.segs[a.evals[e].seg];
     Real g;
     int j;
-    pass2_best<Real, PL>(v, tile, r, p, g, j);
+    pass2_best<Real, PL>(v, tile, r, p, g, j, sg.j_lo, sg.j_hi);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       const Real go = __shfl_xor(g, off, 64);
@@ -363,9 +364,10 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
       pass2_load<Real, PL>(v, ws, tile, r, p);
       run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, lds + r * LP2, lds + (PL::RW + r) * LP2, tw2,
                                                                    p);
+      const SegDesc& sg = a.segs[a.evals[e].seg];
       Real g;
       int j;
-      pass2_best<Real, PL>(v, tile, r, p, g, j);
+      pass2_best<Real, PL>(v, tile, r, p, g, j, sg.j_lo, sg.j_hi);
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         const Real go = __shfl_xor(g, off, 64);

@@ -374,6 +374,8 @@ int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples, const dou
   sd.plan = plan;
   sd.registered = 1;
   sd.df = df;
+  sd.j_lo = 0;
+  sd.j_hi = n_samples;
   for (int i = 0; i < D; ++i) {
     if (!(sigma2[i] > 0) || !std::isfinite(sigma2[i])) {
       hipFree(y);
@@ -392,6 +394,22 @@ int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples, const dou
   ctx->seg_b[seg_id] = b;
   ctx->plan_refs[plan]++;
   return FCAS_OK;
+}
+
+int fcas_set_segment_range(fcas_ctx* ctx, int32_t seg_id, int64_t j_lo, int64_t j_hi) {
+  if (!ctx) return fail(FCAS_EINVAL, "context is NULL");
+  if (seg_id < 0 || seg_id >= ctx->cfg.max_segments)
+    return fail(FCAS_ENOSEG, "segment id %d out of range [0, %d)", seg_id, ctx->cfg.max_segments);
+  SegDesc& sd = ctx->h_segs[seg_id];
+  if (!sd.registered) return fail(FCAS_ENOSEG, "segment %d is not registered", seg_id);
+  if (j_lo < 0 || j_hi > sd.n || j_lo >= j_hi)
+    return fail(FCAS_EINVAL, "need 0 <= j_lo < j_hi <= %lld, got [%lld, %lld)", (long long)sd.n, (long long)j_lo,
+                (long long)j_hi);
+  hipSetDevice(ctx->device);
+  sd.j_lo = j_lo;
+  sd.j_hi = j_hi;
+  hipError_t e = hipMemcpy(ctx->d_segs + seg_id, &sd, sizeof sd, hipMemcpyHostToDevice);
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "segment descriptor upload");
 }
 
 }  // extern "C"

@@ -37,6 +37,7 @@ struct SegDesc {
   int32_t registered;   // 1 once fcas_set_segment has completed
   double df;            // 1 / T
   double sigma[kMaxDet];
+  int64_t j_lo, j_hi;   // coalescence samples searched: j_lo <= j < j_hi
 };
 
 // Per parameter point, written by the set-up kernel.
@@ -420,10 +421,12 @@ FCAS_HD void pass2_load(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int 
   pass2_twiddle<Real, PL>(v, tile, r, p);
 }
 
-// Pass 2 epilogue: Gamma^2_j = |a_0|^2 + |a_1|^2 at j = j1 + N1 (p + q P2);
-// the thread's largest value and, among equal values, its smallest j.
+// Pass 2 epilogue: Gamma^2_j = |a_0|^2 + |a_1|^2 at j = j1 + N1 (p + q P2),
+// for j_lo <= j < j_hi; the thread's largest value and, among equal values,
+// its smallest j (value -1 if none of its samples is in range).
 template <typename Real, class PL>
-FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p, Real& best, int& best_j) {
+FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p, Real& best, int& best_j,
+                        int64_t j_lo = 0, int64_t j_hi = PL::N) {
   const int j1 = tile * PL::RW + r;
   best = (Real)-1;
   best_j = 0x7fffffff;
@@ -431,7 +434,7 @@ FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p
   for (int q = 0; q < PL::E2; ++q) {
     const Real g = norm2(v[0][q]) + norm2(v[1][q]);
     const int j = j1 + PL::N1 * (p + q * PL::P2);
-    if (g > best) {   // j grows with q: ties keep the smaller j
+    if (g > best && j >= j_lo && j < j_hi) {   // j grows with q: ties keep the smaller j
       best = g;
       best_j = j;
     }

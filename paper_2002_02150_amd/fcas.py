@@ -26,7 +26,7 @@ MAX_DET = 8
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP", -5: "ENOMEM", -6: "ECAPACITY"}
 
 EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_plan_count",
-            "fcas_plan_info", "fcas_select_plan", "fcas_set_segment",
+            "fcas_plan_info", "fcas_select_plan", "fcas_set_segment", "fcas_set_segment_range",
             "fitness_eval_batch", "fitness_grad_batch", "fitness_polish", "pso_init", "pso_step", "pso_best",
             "fcas_inject", "fcas_evaluated", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
 
@@ -83,6 +83,7 @@ def library():
         "fcas_plan_info": ([i32] + [ctypes.POINTER(i64)] + [ctypes.POINTER(i32)] * 6, ctypes.c_int),
         "fcas_select_plan": ([vp, i32, i32, i32], ctypes.c_int),
         "fcas_set_segment": ([vp, i32, i64, vp, vp, vp], ctypes.c_int),
+        "fcas_set_segment_range": ([vp, i32, i64, i64], ctypes.c_int),
         "fitness_eval_batch": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "fitness_grad_batch": ([vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "fitness_polish": ([vp, i32, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp], ctypes.c_int),
@@ -223,6 +224,10 @@ class Context:
         _want(psd, torch.float64, (self.n_det, half), self.device, "psd")
         _check(library().fcas_set_segment(self._h, int(seg_id), n, _ptr(xf), _ptr(psd), _stream(self.device)))
         self.seg_samples[int(seg_id)] = n
+
+    def set_segment_range(self, seg_id, j_lo, j_hi):
+        """Search coalescence samples j_lo <= j < j_hi of segment seg_id only."""
+        _check(library().fcas_set_segment_range(self._h, int(seg_id), int(j_lo), int(j_hi)))
 
     def _batch_args(self, theta, seg):
         n = theta.shape[0]

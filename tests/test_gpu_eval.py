@@ -210,3 +210,37 @@ def test_library_injection_matches_oracle_signal_model():
     got = xf.cpu().numpy()
     assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
     ctx.close()
+
+
+def test_coalescence_range_restriction():
+    """fcas_set_segment_range limits the maximum over t_c to j_lo <= j < j_hi;
+    the GPU follows the oracle with the same restriction, bad ranges are refused."""
+    require_gpu()
+    from paper_2002_02150_amd import FcasError
+    case = Case("HLVK", 16384, 2048.0, snr=12.0, cfg=17)
+    rng = np.random.default_rng(8)
+    th = thetas_for(case, rng, n_near=8, n_uniform=8, extras=False)
+    ctx = make_ctx(case, 0, max_batch=len(th), max_segments=2)
+    upload(ctx, 0, case)
+    t = torch.from_numpy(th).to(dev())
+    seg = torch.zeros(len(th), dtype=torch.int32, device=dev())
+    tc = case.inj["tc_sample"]
+    for lo, hi in ((4096, 12288), (0, 1), (16383, 16384), (max(tc - 5, 0), min(tc + 6, 16384))):
+        ctx.set_segment_range(0, lo, hi)
+        f, j = ctx.eval(t, seg)
+        f, j = f.cpu().numpy(), j.cpu().numpy()
+        assert np.all((j >= lo) & (j < hi))
+        fo, jo = oracle_eval_range(case, th, (lo, hi))
+        assert_parity(case, th, f, j, fo, jo, 1e-4)
+    for bad in ((-1, 10), (10, 10), (0, 16385)):
+        with pytest.raises(FcasError):
+            ctx.set_segment_range(0, *bad)
+    with pytest.raises(FcasError):
+        ctx.set_segment_range(1, 0, 10)   # not registered
+    ctx.close()
+
+
+def oracle_eval_range(case, thetas, j_range):
+    import synth
+    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    return F.fitness_batch(case.seg, case.net.pos_m, case.net.tensor, thetas, np.array(lo), np.array(hi), j_range)

@@ -328,3 +328,18 @@ def test_search_box_covers_mass_square():
     assert lo[2] <= g["tau0_s"][0] and hi[2] >= g["tau0_s"][1]
     assert lo[3] <= g["tau15_s"][0] and hi[3] >= g["tau15_s"][1]
     assert hi[2] - g["tau0_s"][1] < 1e-3 and g["tau0_s"][0] - lo[2] < 1e-3
+
+
+def test_restricted_coalescence_range():
+    """The maximum over a sample range is the maximum of that part of the series,
+    never above the unrestricted one and equal to it when the range holds j*."""
+    case = Case("HLV", 4096, 1024.0, snr=12.0, cfg=101)
+    th = case.theta0
+    g = case.series(th)
+    f_all, j_all = case.fitness(th)
+    for lo, hi in ((0, 100), (1000, 3000), (j_all, j_all + 1), (max(j_all - 7, 0), min(j_all + 9, 4096))):
+        f, j = F.fitness(case.seg, case.net.pos_m, case.net.tensor, th, j_range=(lo, hi))
+        assert lo <= j < hi and f == pytest.approx(np.max(g[lo:hi]), rel=1e-15)
+        assert f <= f_all
+        if lo <= j_all < hi:
+            assert j == j_all and f == f_all
