@@ -3,8 +3,9 @@
 One step is one iteration of the PSO search of the 4-detector, 64 s, 2048 Hz
 configuration (131072 samples per detector, SNR-10 injection): the fitness of
 8 runs x 40 particles (320 evaluations), the swarm update and the best of the
-runs, captured once as a HIP graph and replayed; the timed region ends with
-the gradient polish of the best point.  value = fitness evaluations of the
+runs, captured as HIP graphs of 20 iterations and replayed; by default the
+timed region is one whole search (2000 iterations) and ends with the gradient
+polish of the best point.  value = fitness evaluations of the
 particles per second over the timed region (inputs resident in HBM).  A second
 timed region launches the same steps eagerly with HIP events around the FFT
 pass kernels, for the roofline figures.
@@ -33,12 +34,14 @@ KERNEL_SOURCES = ("fft_core.hpp", "fitness_tiles.hpp", "plans.hpp", "eval_kernel
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: search 2000 = one whole search, batched 20, gradient 50)")
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
-    ap.add_argument("--schedule", choices=("fused", "two-pass"), default="two-pass")
+    ap.add_argument("--schedule", choices=("fused", "two-pass", "two-streams"), default="two-pass",
+                    help="schedule of the timed search; its kernel-timing region runs the two-stream schedule as two-pass")
     ap.add_argument("--config", choices=("search", "batched", "gradient"), default="search",
                     help="search: the benchmark configuration (default); batched: 256 ragged segments, "
                          "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source")
@@ -56,6 +59,14 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+SCHEDULES = {"fused": 0, "two-pass": 1, "two-streams": 2}
+
+
+def synth_box():
+    import synth
+    return synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+
+
 def make_workload(torch, dev, schedule):
     import synth
     from paper_2002_02150_amd import Context
@@ -68,7 +79,7 @@ def make_workload(torch, dev, schedule):
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi,
                                max_batch=RUNS * PARTICLES, max_samples=N_SAMPLES,
-                               schedule=0 if schedule == "fused" else 1)
+                               schedule=SCHEDULES[schedule])
     xf = torch.from_numpy(noise).to(dev)
     psd_d = torch.from_numpy(np.ascontiguousarray(psd)).to(dev)
     ctx.inject(xf, psd_d, inj["alpha"], inj["delta"], t0, t15, inj["psi"], inj["phi_c"], inj["cos_iota"],
@@ -95,23 +106,37 @@ class Search:
         self.pol_j = torch.empty(1, dtype=torch.int32, device=dev)
         self.graph = None
 
-    def iteration(self, timed=False):
-        self.ctx.set_timing(timed)   # kernel events bracket only the fitness launches
-        self.ctx.eval(self.sw.theta, self.seg, self.f, self.j)
-        self.ctx.set_timing(False)
+    def iteration(self, timed=False, ctx=None):
+        ctx = ctx or self.ctx
+        ctx.set_timing(timed)   # kernel events bracket only the fitness launches
+        ctx.eval(self.sw.theta, self.seg, self.f, self.j)
+        ctx.set_timing(False)
         self.sw.step(self.f, self.j)
         self.sw.best()
 
-    def capture(self):
+    def capture(self, group):
+        """Captures two HIP graphs: `group` iterations, and one iteration."""
         torch = self.torch
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
             self.iteration()
         torch.cuda.current_stream().wait_stream(s)
+        self.group = group
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
+            for _ in range(group):
+                self.iteration()
+        self.graph1 = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph1):
             self.iteration()
+
+    def run(self, steps):
+        """`steps` iterations as graph replays."""
+        for _ in range(steps // self.group):
+            self.graph.replay()
+        for _ in range(steps % self.group):
+            self.graph1.replay()
 
     def polish(self):
         from paper_2002_02150_amd import polish
@@ -121,6 +146,7 @@ class Search:
 
 
 POLISH_STEPS = 10
+GRAPH_GROUP = 20   # PSO iterations per replayed HIP graph
 
 
 def fp64_plain_rate(torch, net, xf, psd_d, thetas, dev):
@@ -186,7 +212,7 @@ def run_batched(a, torch, dev):
     R = n_seg * runs_per_seg
     n = R * PARTICLES
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
-                               max_segments=n_seg, max_samples=max(lengths))
+                               max_segments=n_seg, max_samples=max(lengths), schedule=SCHEDULES[a.schedule])
     gen = torch.Generator(device=dev).manual_seed(20020215 + 3)
     for s_id, N in enumerate(seg_len):
         half = N // 2 + 1
@@ -257,7 +283,7 @@ def run_gradient(a, torch, dev):
     t0, t15 = chirp_times(inj["m1"], inj["m2"], F_LOW)
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
-                               max_samples=N_SAMPLES)
+                               max_samples=N_SAMPLES, schedule=SCHEDULES[a.schedule])
     xf = torch.from_numpy(noise).to(dev)
     psd_d = torch.from_numpy(np.ascontiguousarray(psd)).to(dev)
     ctx.inject(xf, psd_d, inj["alpha"], inj["delta"], t0, t15, inj["psi"], inj["phi_c"], inj["cos_iota"],
@@ -310,6 +336,8 @@ def main():
         sys.exit(2)
     from paper_2002_02150_amd import PsoConfig, Swarm
     dev = torch.device("cuda", 0)
+    if a.steps is None:
+        a.steps = {"search": 2000, "batched": 20, "gradient": 50}[a.config]
     if a.config == "batched":
         return run_batched(a, torch, dev)
     if a.config == "gradient":
@@ -320,36 +348,48 @@ def main():
     search = Search(torch, ctx, sw)
     for _ in range(a.warmup):
         search.iteration()
-    search.capture()          # one more iteration, as a HIP graph
+    search.capture(GRAPH_GROUP)   # one more iteration, then graphs of GRAPH_GROUP and 1 iterations
     torch.cuda.synchronize()
     # timed region 1: K iterations (graph replays) and the polish of the best point
     ev0 = ctx.evaluated()
     t = time.perf_counter()
-    for _ in range(a.steps):
-        search.graph.replay()
+    search.run(a.steps)
     ev_mid = ctx.evaluated()      # synchronises; the polish evaluations are not counted
     search.polish()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     ev1 = ctx.evaluated()
     iterations_done = sw.iteration.item()
-    # timed region 2: K iterations launched eagerly, HIP events around the FFT passes
-    ev2 = ctx.evaluated()
+    # timed region 2: K iterations launched eagerly on one stream (two-pass or
+    # fused schedule, so that each FFT kernel runs alone), HIP events around the
+    # FFT passes
+    kctx = ctx
+    if a.schedule == "two-streams":
+        from paper_2002_02150_amd import Context
+        kctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=synth_box()[0],
+                                    box_hi=synth_box()[1], max_batch=RUNS * PARTICLES, max_samples=N_SAMPLES,
+                                    schedule=SCHEDULES["two-pass"])
+        kctx.set_segment(0, xf, psd_d)
+        search.iteration(ctx=kctx)
+        torch.cuda.synchronize()
+    ev2 = kctx.evaluated()
     t2 = time.perf_counter()
     per_launch = []
     prev = ev2
     for _ in range(a.steps):
-        search.iteration(timed=True)
+        search.iteration(timed=True, ctx=kctx)
         if a.launch_counts:      # synchronises every step: only for pairing with counter runs
-            cur = ctx.evaluated()
+            cur = kctx.evaluated()
             per_launch.append(cur - prev)
             prev = cur
     torch.cuda.synchronize()
     dt2 = time.perf_counter() - t2
-    ev3 = ctx.evaluated()
-    ms1, n1 = ctx.read_timing("pass1")
-    ms2, n2 = ctx.read_timing("pass2")
-    msf, nf = ctx.read_timing("fused")
+    ev3 = kctx.evaluated()
+    ms1, n1 = kctx.read_timing("pass1")
+    ms2, n2 = kctx.read_timing("pass2")
+    msf, nf = kctx.read_timing("fused")
+    if kctx is not ctx:
+        kctx.close()
     evals = a.steps * RUNS * PARTICLES
     # value counts the fitness evaluations performed for the particles inside the
     # rectangle (points that flew out are not evaluated); the polish is timed but

@@ -54,10 +54,16 @@ extern "C" {
                          projection and maximum in FP32                           */
 #define FCAS_FP64 1   /* everything in FP64 (the plain reference path)            */
 
-/* launch schedule of the two FFT passes (FCAS_MIXED only; FP64 is always two-pass) */
+/* launch schedule of the two FFT passes (FUSED: FCAS_MIXED only) */
 #define FCAS_SCHEDULE_FUSED 0     /* one persistent launch per plan, passes pipelined  */
-#define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk
-                                     (the faster one on MI355X: recommended)          */
+#define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk  */
+#define FCAS_SCHEDULE_TWO_STREAMS 2 /* two-pass, with the points of a batch that fits
+                                     the workspace split in two halves whose launches
+                                     run on the caller's stream and on a second,
+                                     library-owned stream (forked from and joined back
+                                     into the caller's stream by events, so the call
+                                     stays capturable into a HIP graph); the halves
+                                     overlap on the device                          */
 
 typedef struct fcas_ctx fcas_ctx;
 
@@ -81,7 +87,7 @@ typedef struct {
   int32_t precision;      /* FCAS_MIXED or FCAS_FP64 */
   int32_t max_batch;      /* largest n accepted by fitness_eval/grad_batch */
   int32_t max_segments;   /* segment ids are 0..max_segments-1 */
-  int32_t schedule;       /* FCAS_SCHEDULE_TWO_PASS or FCAS_SCHEDULE_FUSED */
+  int32_t schedule;       /* FCAS_SCHEDULE_TWO_PASS, _TWO_STREAMS or _FUSED */
   int64_t max_samples;    /* largest segment length N that will be registered */
   int64_t workspace_bytes;/* FFT workspace; 0 = enough for max_batch evaluations
                              of max_samples (batches beyond it run in chunks) */
@@ -194,7 +200,8 @@ typedef struct {
   double* best_x;   /* [R][4]    best position of each run */
   double* best_f;   /* [R]       best fitness of each run */
   int32_t* best_j;  /* [R]       argmax sample at the run's best */
-  int32_t* iteration; /* [1]     iterations taken (pso_init sets 0, pso_step adds 1) */
+  int32_t* iteration; /* [2]     [0]: iterations taken (pso_init sets 0, pso_step adds 1);
+                                [1]: pso_step's tally of finished runs (pso_init sets 0) */
 } fcas_pso_state;
 
 /* Random initial positions / velocities; pbest_f = best_f = -inf.

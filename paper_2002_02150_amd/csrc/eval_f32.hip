@@ -67,11 +67,11 @@ int fused_blocks_per_cu(int plan) {
 }
 
 hipError_t launch_finalize_f32(const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                                  const int32_t* part_j, int n, const int32_t* plan_tiles2, const int32_t* counts,
+                                  const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
                                   unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize<float>, dim3((n + 3) / 4), dim3(256), 0, s, evals, segs,
-                     (const float*)part_g, part_j, n, plan_tiles2, counts, evaluated, fitness, argmax);
+                     (const float*)part_g, part_j, n, plan_parts2, counts, evaluated, fitness, argmax);
   return hipGetLastError();
 }
 

@@ -15,12 +15,34 @@ struct PassArgs {
   const int32_t* list;     // evaluation indices of this plan, in list order
   const int32_t* count;    // number of entries in `list`
   void* ws;                // workspace: cap slots of 2 N complex
-  void* part_g;            // [max_batch][kMaxTiles2] partial maxima (Real)
-  int32_t* part_j;         // [max_batch][kMaxTiles2] their samples
+  void* part_g;            // [max_batch][kMaxParts2] partial maxima (Real)
+  int32_t* part_j;         // [max_batch][kMaxParts2] their samples
   int32_t n_det;
-  int32_t chunk_begin;     // first list position handled by this launch
-  int32_t cap;             // workspace slots
+  int32_t chunk_begin;     // first list position of this chunk
+  int32_t cap;             // workspace slots (positions per chunk)
+  int32_t split_part;      // this launch takes share split_part of split_parts of the chunk
+  int32_t split_parts;     // (1: the whole chunk)
 };
+
+// Narrows `a` to the list positions one launch handles: the chunk
+// [chunk_begin, chunk_begin + cap) of the plan's list, and within it share
+// split_part of split_parts near-equal shares (sized from the count the set-up
+// kernel wrote, so both passes of a share agree).  Moves chunk_begin and ws to
+// the share's first position and returns the number of positions.
+template <typename Real, class PL>
+__device__ __forceinline__ int launch_span(PassArgs& a) {
+  int cnt = *a.count - a.chunk_begin;
+  cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
+  if (a.split_parts > 1) {
+    const int per = (cnt + a.split_parts - 1) / a.split_parts;
+    const int first = a.split_part * per;
+    cnt -= first;
+    cnt = cnt < 0 ? 0 : (cnt > per ? per : cnt);
+    a.chunk_begin += first;
+    a.ws = (cplx<Real>*)a.ws + (int64_t)first * 2 * PL::N;
+  }
+  return cnt;
+}
 
 // ---------------------------------------------------------------------------
 // Pass 1: prologue (template phase, delays, projection) + length-N1 column
@@ -83,16 +105,34 @@ __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* bu
 }
 
 template <typename Real, class PL, int DT>
-__global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
+__device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, const PassArgs& a, int item, int c,
+                                                 int p) {
+  const int slot = item / PL::TILES1;
+  const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
+  pass1_fetch<Real, PL, DT>(d, a.segs[ev.seg], item - slot * PL::TILES1, c, p);
+}
+
+template <typename Real, class PL, int DT>
+__device__ __forceinline__ void pass1_item(const Pass1Data<Real, PL, DT>& d, const PassArgs& a, int item, int c,
+                                           int p, cplx<Real>* buf0, cplx<Real>* buf1, const cplx<Real>* tw) {
+  const int slot = item / PL::TILES1;
+  const int tile = item - slot * PL::TILES1;
+  const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
+  cplx<Real> v[2][PL::E1];
+  pass1_compute<Real, PL, DT>(v, d, ev);
+  run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
+  pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
+}
+
+template <typename Real, class PL, int DT>
+__global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))) k_pass1(PassArgs a) {
   constexpr int LP = lds_padded_len(PL::N1);
   __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::C * LP];
   __shared__ cplx<Real> tw[PL::N1];
   const int tid = threadIdx.x;
   for (int m = tid; m < PL::N1; m += PL::T1) tw[m] = twiddle<Real>(m, PL::N1);
   __syncthreads();
-  int cnt = *a.count - a.chunk_begin;
-  cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
-  const int items = cnt * PL::TILES1;
+  const int items = launch_span<Real, PL>(a) * PL::TILES1;
   const int c = tid % PL::C, p = tid / PL::C;
   cplx<Real>* buf0 = lds + c * LP;
   cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::C + c) * LP : buf0;
@@ -101,27 +141,12 @@ __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
     // this one is transformed
     Pass1Data<Real, PL, DT> nxt;
     int item = blockIdx.x;
-    if (item < items) {
-      const int slot = item / PL::TILES1;
-      const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
-      pass1_fetch<Real, PL, DT>(nxt, a.segs[ev.seg], item - slot * PL::TILES1, c, p);
-    }
+    if (item < items) pass1_fetch_item<Real, PL, DT>(nxt, a, item, c, p);
     for (; item < items; item += gridDim.x) {
-      const int slot = item / PL::TILES1;
-      const int tile = item - slot * PL::TILES1;
-      const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
       const Pass1Data<Real, PL, DT> cur = nxt;
       const int next = item + gridDim.x;
-      if (next < items) {
-        const int ns = next / PL::TILES1;
-        const EvalDesc& en = a.evals[a.list[a.chunk_begin + ns]];
-        pass1_fetch<Real, PL, DT>(nxt, a.segs[en.seg], next - ns * PL::TILES1, c, p);
-      }
-      cplx<Real> v[2][PL::E1];
-      pass1_compute<Real, PL, DT>(v, cur, ev);
-      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
-      cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
-      pass1_store<Real, PL>(v, ws, tile, c, p);
+      if (next < items) pass1_fetch_item<Real, PL, DT>(nxt, a, next, c, p);
+      pass1_item<Real, PL, DT>(cur, a, item, c, p, buf0, buf1, tw);
     }
   } else {
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
@@ -140,80 +165,75 @@ __global__ void __launch_bounds__(PL::T1) k_pass1(PassArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Pass 2: length-N2 row FFTs, |a_0|^2 + |a_1|^2 and its maximum over the RW
-// rows of one work item -> one partial (value, sample) per item.
+// Pass 2: length-N2 row FFTs, |a_0|^2 + |a_1|^2 and its maximum over the rows
+// of one work item -> one partial (value, sample) per wavefront.  Every row
+// transform lies inside one wavefront, so the items need no work-group
+// barrier.
 // ---------------------------------------------------------------------------
+template <typename Real, class PL>
+__device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const PassArgs& a, int item,
+                                           cplx<Real>* buf0, cplx<Real>* buf1, const cplx<Real>* tw, int r, int p,
+                                           int lane, int wave) {
+  constexpr int NW = PL::T2 / 64;
+  const int slot = item / PL::TILES2;
+  const int tile = item - slot * PL::TILES2;
+  const int e = a.list[a.chunk_begin + slot];
+  pass2_twiddle<Real, PL>(v, tile, r, p);
+  run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, true>(v, buf0, buf1, tw, p);
+  const SegDesc& sg = a.segs[a.evals[e].seg];
+  Real g;
+  int j;
+  pass2_best<Real, PL>(v, tile, r, p, g, j, sg.j_lo, sg.j_hi);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const Real go = __shfl_xor(g, off, 64);
+    const int jo = __shfl_xor(j, off, 64);
+    if (better(go, jo, g, j)) {
+      g = go;
+      j = jo;
+    }
+  }
+  if (lane == 0) {
+    const int64_t o = (int64_t)e * kMaxParts2 + tile * NW + wave;
+    ((Real*)a.part_g)[o] = g;
+    a.part_j[o] = j;
+  }
+}
+
+template <typename Real, class PL>
+__device__ __forceinline__ void pass2_fetch_item(cplx<Real> (&v)[2][PL::E2], const PassArgs& a, int item, int r,
+                                                 int p) {
+  const int slot = item / PL::TILES2;
+  pass2_fetch<Real, PL>(v, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, item - slot * PL::TILES2, r, p);
+}
+
 template <typename Real, class PL>
 __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
   constexpr int LP = lds_padded_len(PL::N2);
-  constexpr int NW = PL::T2 / 64;
-  // every row transform lies inside one wavefront: P2 threads, P2 divides 64
-  constexpr bool WAVE = (64 % PL::P2) == 0;
   __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::RW * LP];
   __shared__ cplx<Real> tw[PL::N2];
-  __shared__ Real red_g[NW > 0 ? NW : 1];
-  __shared__ int red_j[NW > 0 ? NW : 1];
   const int tid = threadIdx.x;
   for (int m = tid; m < PL::N2; m += PL::T2) tw[m] = twiddle<Real>(m, PL::N2);
   __syncthreads();
-  int cnt = *a.count - a.chunk_begin;
-  cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
-  const int items = cnt * PL::TILES2;
+  const int items = launch_span<Real, PL>(a) * PL::TILES2;
   const int p = tid % PL::P2, r = tid / PL::P2;
   cplx<Real>* buf0 = lds + r * LP;
   cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::RW + r) * LP : buf0;
   const int lane = tid & 63, wave = tid >> 6;
-  // software pipeline: the rows of the next item are fetched while this one is transformed
-  cplx<Real> nxt[2][PL::E2];
+  const int G = gridDim.x;
+  // software pipeline over two register sets: the rows of the next item are
+  // fetched while this one is transformed
+  cplx<Real> va[2][PL::E2], vb[2][PL::E2];
   int item = blockIdx.x;
-  if (item < items) {
-    const int slot = item / PL::TILES2;
-    pass2_fetch<Real, PL>(nxt, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, item - slot * PL::TILES2, r, p);
-  }
-  for (; item < items; item += gridDim.x) {
-    const int slot = item / PL::TILES2;
-    const int tile = item - slot * PL::TILES2;
-    const int e = a.list[a.chunk_begin + slot];
-    cplx<Real> v[2][PL::E2];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-      for (int q = 0; q < PL::E2; ++q) v[s][q] = nxt[s][q];
-    const int next = item + gridDim.x;
-    if (next < items) {
-      const int ns = next / PL::TILES2;
-      pass2_fetch<Real, PL>(nxt, (const cplx<Real>*)a.ws + (int64_t)ns * 2 * PL::N, next - ns * PL::TILES2, r, p);
-    }
-    pass2_twiddle<Real, PL>(v, tile, r, p);
-    run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf0, buf1, tw, p);
-    const SegDesc& sg = a.segs[a.evals[e].seg];
-    Real g;
-    int j;
-    pass2_best<Real, PL>(v, tile, r, p, g, j, sg.j_lo, sg.j_hi);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const Real go = __shfl_xor(g, off, 64);
-      const int jo = __shfl_xor(j, off, 64);
-      if (better(go, jo, g, j)) {
-        g = go;
-        j = jo;
-      }
-    }
-    if (lane == 0) {
-      red_g[wave] = g;
-      red_j[wave] = j;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      for (int w = 1; w < NW; ++w)
-        if (better(red_g[w], red_j[w], g, j)) {
-          g = red_g[w];
-          j = red_j[w];
-        }
-      ((Real*)a.part_g)[(int64_t)e * kMaxTiles2 + tile] = g;
-      a.part_j[(int64_t)e * kMaxTiles2 + tile] = j;
-    }
-    __syncthreads();
+  if (item < items) pass2_fetch_item<Real, PL>(va, a, item, r, p);
+  while (item < items) {
+    const int next = item + G;
+    if (next < items) pass2_fetch_item<Real, PL>(vb, a, next, r, p);
+    pass2_item<Real, PL>(va, a, item, buf0, buf1, tw, r, p, lane, wave);
+    if (next >= items) break;
+    item = next + G;
+    if (item < items) pass2_fetch_item<Real, PL>(va, a, item, r, p);
+    pass2_item<Real, PL>(vb, a, next, buf0, buf1, tw, r, p, lane, wave);
   }
 }
 
@@ -224,15 +244,20 @@ template <typename Real>
 __global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ evals,
                                                   const SegDesc* __restrict__ segs, const Real* __restrict__ part_g,
                                                   const int32_t* __restrict__ part_j, int n,
-                                                  const int32_t* __restrict__ plan_tiles2,
-                                                  const int32_t* __restrict__ counts,
+                                                  const int32_t* __restrict__ plan_parts2,
+                                                  int32_t* __restrict__ counts,
                                                   unsigned long long* __restrict__ evaluated,
                                                   double* __restrict__ fitness, int32_t* __restrict__ argmax) {
   const int lane = threadIdx.x & 63;
   const int e = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {   // running total of points evaluated (inside the rectangle)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // running total of points evaluated (inside the rectangle); the passes of
+    // this call are done with the list counts, which start the next call at 0
     unsigned long long t = 0;
-    for (int p = 0; p < kNumPlans; ++p) t += (unsigned long long)counts[p];
+    for (int p = 0; p < kNumPlans; ++p) {
+      t += (unsigned long long)counts[p];
+      counts[p] = 0;
+    }
     atomicAdd(evaluated, t);
   }
   if (e >= n) return;
@@ -245,12 +270,12 @@ __global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ e
     }
     return;
   }
-  const int nt = plan_tiles2[ev.plan];
+  const int nt = plan_parts2[ev.plan];
   Real g = (Real)-1;
   int j = 0x7fffffff;
   for (int t = lane; t < nt; t += 64) {
-    const Real go = part_g[(int64_t)e * kMaxTiles2 + t];
-    const int jo = part_j[(int64_t)e * kMaxTiles2 + t];
+    const Real go = part_g[(int64_t)e * kMaxParts2 + t];
+    const int jo = part_j[(int64_t)e * kMaxParts2 + t];
     if (better(go, jo, g, j)) {
       g = go;
       j = jo;
@@ -329,8 +354,6 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
   __shared__ cplx<Real> lds[LDSN];
   __shared__ cplx<Real> tw1[PL::N1];
   __shared__ cplx<Real> tw2[PL::N2];
-  __shared__ Real red_g[NW];
-  __shared__ int red_j[NW];
   const PassArgs& a = f.p;
   const int tid = threadIdx.x;
   for (int m = tid; m < PL::N1; m += PL::T1) tw1[m] = twiddle<Real>(m, PL::N1);
@@ -374,13 +397,10 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
         const int jo = __shfl_xor(j, off, 64);
         if (better(go, jo, g, j)) { g = go; j = jo; }
       }
-      if (lane == 0) { red_g[wave] = g; red_j[wave] = j; }
-      __syncthreads();
-      if (tid == 0) {
-        for (int w = 1; w < NW; ++w)
-          if (better(red_g[w], red_j[w], g, j)) { g = red_g[w]; j = red_j[w]; }
-        ((Real*)a.part_g)[(int64_t)e * kMaxTiles2 + tile] = g;
-        a.part_j[(int64_t)e * kMaxTiles2 + tile] = j;
+      if (lane == 0) {
+        const int64_t o = (int64_t)e * kMaxParts2 + tile * NW + wave;
+        ((Real*)a.part_g)[o] = g;
+        a.part_j[o] = j;
       }
       signal_count(f.done2 + ep);
     }

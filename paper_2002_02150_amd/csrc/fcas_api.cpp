@@ -58,9 +58,9 @@ struct fcas_ctx {
   EvalDesc* d_evals = nullptr;
   int32_t* d_lists = nullptr;    // [kNumPlans][max_batch]
   int32_t* d_counts = nullptr;   // [kNumPlans]
-  void* d_part_g = nullptr;      // [max_batch][kMaxTiles2]
+  void* d_part_g = nullptr;      // [max_batch][kMaxParts2]
   int32_t* d_part_j = nullptr;
-  int32_t* d_plan_tiles2 = nullptr;
+  int32_t* d_plan_parts2 = nullptr;
   int32_t* d_err = nullptr;
   unsigned long long* d_evaluated = nullptr;   // running total of points evaluated
   double* d_sigma2 = nullptr;    // [FCAS_MAX_DET] scratch for segment registration
@@ -77,6 +77,8 @@ struct fcas_ctx {
   int n_cu = 0;                     // compute units of the device
   int fused_cap[kNumPlans] = {0};   // resident work-groups of each fused kernel (0 = not queried)
   int32_t* d_done = nullptr;        // [kNumPlans][2][max_batch] fused-schedule tile counters
+  hipStream_t aux = nullptr;        // second stream of the two-stream schedule
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
   std::vector<TimedPair> t_pass1, t_pass2, t_fused;
   int grid1[kNumPlans], grid2[kNumPlans];   // persistent grid sizes of the two passes
@@ -125,8 +127,9 @@ int validate_config(const fcas_config* c) {
   if (plan_for_length(c->max_samples) < 0)
     return fail(FCAS_EUNSUPPORTED_N, "max_samples %lld has no FFT plan", (long long)c->max_samples);
   if (c->workspace_bytes < 0) return fail(FCAS_EINVAL, "workspace_bytes must be >= 0");
-  if (c->schedule != FCAS_SCHEDULE_FUSED && c->schedule != FCAS_SCHEDULE_TWO_PASS)
-    return fail(FCAS_EINVAL, "schedule must be FCAS_SCHEDULE_FUSED or FCAS_SCHEDULE_TWO_PASS");
+  if (c->schedule != FCAS_SCHEDULE_FUSED && c->schedule != FCAS_SCHEDULE_TWO_PASS &&
+      c->schedule != FCAS_SCHEDULE_TWO_STREAMS)
+    return fail(FCAS_EINVAL, "schedule must be FCAS_SCHEDULE_FUSED, _TWO_PASS or _TWO_STREAMS");
   for (int d = 0; d < 4; ++d) {
     if (!std::isfinite(c->box_lo[d]) || !std::isfinite(c->box_hi[d]) || !(c->box_hi[d] >= c->box_lo[d]))
       return fail(FCAS_EINVAL, "search box coordinate %d must satisfy lo <= hi (finite)", d);
@@ -149,7 +152,7 @@ int free_all(fcas_ctx* c) {
   for (void* p : c->seg_y) if (p) hipFree(p);
   for (double* p : c->seg_b) if (p) hipFree(p);
   void* bufs[] = {c->d_net, c->d_segs, c->d_evals, c->d_lists, c->d_counts, c->d_part_g,
-                  c->d_part_j, c->d_plan_tiles2, c->d_err, c->d_sigma2, c->d_ws,
+                  c->d_part_j, c->d_plan_parts2, c->d_err, c->d_sigma2, c->d_ws,
                   c->d_pol_grad, c->d_pol_cand, c->d_pol_seg, c->d_pol_f, c->d_pol_j, c->d_evaluated,
                   c->d_done};
   for (void* p : bufs) if (p) hipFree(p);
@@ -157,6 +160,9 @@ int free_all(fcas_ctx* c) {
   for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_pass2) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_fused) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->aux) hipStreamDestroy(c->aux);
   return FCAS_OK;
 }
 
@@ -234,7 +240,8 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
     c->grid1[i] = c->grid2[i] = kDefaultGrid;
     c->chosen[i] = i;
   }
-  c->schedule = (c->prec == 0 && cfg->schedule == FCAS_SCHEDULE_FUSED) ? FCAS_SCHEDULE_FUSED : FCAS_SCHEDULE_TWO_PASS;
+  c->schedule = cfg->schedule == FCAS_SCHEDULE_FUSED ? (c->prec == 0 ? FCAS_SCHEDULE_FUSED : FCAS_SCHEDULE_TWO_PASS)
+                                                      : cfg->schedule;
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
     c->n_cu = 1;
   c->elt = c->prec ? 16 : 8;
@@ -264,9 +271,9 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
       (rc = dev_alloc(&c->d_evals, sizeof(EvalDesc) * B)) ||
       (rc = dev_alloc(&c->d_lists, sizeof(int32_t) * (size_t)kNumPlans * B)) ||
       (rc = dev_alloc(&c->d_counts, sizeof(int32_t) * kNumPlans)) ||
-      (rc = dev_alloc(&c->d_part_g, part_elt * (size_t)B * kMaxTiles2)) ||
-      (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * kMaxTiles2)) ||
-      (rc = dev_alloc(&c->d_plan_tiles2, sizeof(int32_t) * kNumPlans)) ||
+      (rc = dev_alloc(&c->d_part_g, part_elt * (size_t)B * kMaxParts2)) ||
+      (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * kMaxParts2)) ||
+      (rc = dev_alloc(&c->d_plan_parts2, sizeof(int32_t) * kNumPlans)) ||
       (rc = dev_alloc(&c->d_err, sizeof(int32_t))) || (rc = dev_alloc(&c->d_sigma2, sizeof(double) * FCAS_MAX_DET)) ||
       (rc = dev_alloc(&c->d_ws, ws)) || (rc = alloc_grad_buffers(c->grad, B, net->n_det)) ||
       (rc = dev_alloc(&c->d_pol_grad, sizeof(double) * 4 * B)) ||
@@ -281,12 +288,21 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
     g_last_error = msg;
     return rc;
   }
-  int32_t tiles2[kNumPlans];
-  for (int i = 0; i < kNumPlans; ++i) tiles2[i] = kPlans[i].tiles2[c->prec];
+  if (c->schedule == FCAS_SCHEDULE_TWO_STREAMS &&
+      ((e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking)) != hipSuccess ||
+       (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
+       (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess)) {
+    rc = hip_fail(e, "second stream of the two-stream schedule");
+    free_all(c);
+    delete c;
+    return rc;
+  }
+  int32_t parts2[kNumPlans];
+  for (int i = 0; i < kNumPlans; ++i) parts2[i] = kPlans[i].parts2[c->prec];
   if ((e = hipMemcpy(c->d_net, &h, sizeof(NetDesc), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(c->d_segs, c->h_segs.data(), sizeof(SegDesc) * cfg->max_segments, hipMemcpyHostToDevice)) !=
           hipSuccess ||
-      (e = hipMemcpy(c->d_plan_tiles2, tiles2, sizeof tiles2, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(c->d_plan_parts2, parts2, sizeof parts2, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_err, 0, sizeof(int32_t))) != hipSuccess ||
       (e = hipMemset(c->d_evaluated, 0, sizeof(unsigned long long))) != hipSuccess ||
       (e = hipMemset(c->d_counts, 0, sizeof(int32_t) * kNumPlans)) != hipSuccess) {
@@ -373,6 +389,7 @@ int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples, const dou
   sd.k_hi = k_hi;
   sd.plan = plan;
   sd.registered = 1;
+  sd.dk1 = (int32_t)(kPlans[plan].n / kPlans[plan].e1);
   sd.df = df;
   sd.j_lo = 0;
   sd.j_hi = n_samples;
@@ -432,12 +449,14 @@ hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t 
   return e;
 }
 
-// Enqueues the per-point set-up (descriptors and per-plan work lists).
-int enqueue_setup(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, hipStream_t s) {
+// Enqueues the per-point set-up: descriptors and, with build_lists, the
+// per-plan work lists (their counts are zero between calls: the context starts
+// with zeros and every finalize clears them once the passes are done).
+int enqueue_setup(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, hipStream_t s,
+                  bool build_lists = true) {
   hipError_t e;
-  if ((e = launch_zero_i32(ctx->d_counts, kNumPlans, s)) != hipSuccess) return hip_fail(e, "zero counters");
   if ((e = launch_setup(ctx->d_net, ctx->d_segs, d_theta, d_seg, n, ctx->d_evals, ctx->d_lists, ctx->d_counts,
-                        ctx->cfg.max_batch, ctx->d_err, s)) != hipSuccess)
+                        ctx->cfg.max_batch, build_lists ? 1 : 0, ctx->d_err, s)) != hipSuccess)
     return hip_fail(e, "set-up launch");
   return FCAS_OK;
 }
@@ -454,6 +473,8 @@ PassArgs pass_args(fcas_ctx* ctx, int plan, int cap) {
   a.n_det = ctx->net.n_det;
   a.chunk_begin = 0;
   a.cap = cap;
+  a.split_part = 0;
+  a.split_parts = 1;
   return a;
 }
 
@@ -505,8 +526,22 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
   if (ctx->schedule == FCAS_SCHEDULE_FUSED &&
       (e = launch_zero_i32(ctx->d_done, 2 * kNumPlans * ctx->cfg.max_batch, s)) != hipSuccess)
     return hip_fail(e, "zero tile counters");
+  // Two-stream schedule: fork after the set-up; between plans (which reuse the
+  // workspace from its start) both streams wait for each other; join before
+  // finalize.
+  const bool split = ctx->schedule == FCAS_SCHEDULE_TWO_STREAMS && n >= 2;
+  auto fork = [&]() {
+    return (e = hipEventRecord(ctx->ev_fork, s)) == hipSuccess && (e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0)) == hipSuccess;
+  };
+  auto join = [&]() {
+    return (e = hipEventRecord(ctx->ev_join, ctx->aux)) == hipSuccess && (e = hipStreamWaitEvent(s, ctx->ev_join, 0)) == hipSuccess;
+  };
+  if (split && !fork()) return hip_fail(e, "fork of the second stream");
+  bool first_plan = true;
   for (int plan = 0; plan < kNumPlans; ++plan) {
     if (ctx->plan_refs[plan] <= 0) continue;
+    if (split && !first_plan && !(join() && fork())) return hip_fail(e, "synchronisation of the two streams");
+    first_plan = false;
     const PlanInfo& pi = kPlans[plan];
     const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
     int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
@@ -515,26 +550,41 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
       if ((rc = enqueue_fused(ctx, plan, n, cap, s))) return rc;
       continue;
     }
-    PassArgs a{};
-    a.segs = ctx->d_segs;
-    a.evals = ctx->d_evals;
-    a.list = ctx->d_lists + (size_t)plan * ctx->cfg.max_batch;
-    a.count = ctx->d_counts + plan;
-    a.ws = ctx->d_ws;
-    a.part_g = ctx->d_part_g;
-    a.part_j = ctx->d_part_j;
-    a.n_det = ctx->net.n_det;
-    a.cap = cap;
-    for (int begin = 0; begin < n; begin += cap) {
-      a.chunk_begin = begin;
-      const int m = std::min(cap, n - begin);
+    PassArgs a = pass_args(ctx, plan, cap);
+    if (split && n <= cap) {
+      // one chunk, split in two shares: share 0 on the caller's stream, share 1 on the second stream
+      a.split_parts = 2;
+      const int m = (n + 1) / 2;
       const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
       const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
-      if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
-      if ((e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
+      for (int part = 0; part < 2; ++part) {
+        hipStream_t sp = part == 0 ? s : ctx->aux;
+        a.split_part = part;
+        if ((e = timed_launch(ctx, ctx->t_pass1, sp, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
+        if ((e = timed_launch(ctx, ctx->t_pass2, sp, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
+      }
+      continue;
+    }
+    // Chunks of the workspace size; with two streams (and room for two
+    // evaluations), chunks of half of it alternate between the streams, each
+    // stream on its own half.
+    const bool alternate = split && cap >= 2;
+    const int step = alternate ? cap / 2 : cap;
+    a.cap = step;
+    for (int begin = 0, k = 0; begin < n; begin += step, ++k) {
+      const bool second = alternate && (k & 1);
+      a.chunk_begin = begin;
+      a.ws = (char*)ctx->d_ws + (second ? (size_t)step * slot_bytes : 0);
+      const int m = std::min(step, n - begin);
+      const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
+      const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
+      hipStream_t sp = second ? ctx->aux : s;
+      if ((e = timed_launch(ctx, ctx->t_pass1, sp, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
+      if ((e = timed_launch(ctx, ctx->t_pass2, sp, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
     }
   }
-  if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->d_plan_tiles2,
+  if (split && !join()) return hip_fail(e, "join of the second stream");
+  if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->d_plan_parts2,
                            ctx->d_counts, ctx->d_evaluated, d_fitness, d_argmax, s)) != hipSuccess)
     return hip_fail(e, "finalize launch");
   return FCAS_OK;
@@ -584,7 +634,7 @@ int fitness_polish(fcas_ctx* ctx, int32_t n, double* d_theta, const int32_t* d_s
   if ((rc = enqueue_eval(ctx, n, d_theta, d_seg, d_fitness, d_argmax, s))) return rc;
   for (int step = 0; step < n_steps; ++step) {
     // descriptors of the current points (their maximising samples are already in d_argmax)
-    if (step > 0 && (rc = enqueue_setup(ctx, n, d_theta, d_seg, s))) return rc;
+    if (step > 0 && (rc = enqueue_setup(ctx, n, d_theta, d_seg, s, false))) return rc;
     if ((e = launch_gradient(ctx->prec, ctx->grad, ctx->d_net, ctx->d_segs, ctx->d_evals, d_theta, d_argmax, n,
                              ctx->net.n_det, ctx->d_pol_grad, s)) !=
             hipSuccess ||
@@ -681,9 +731,9 @@ hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s
 hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_finalize_f32(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
-                               const int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
+                               int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 hipError_t launch_finalize_f64(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
-                               const int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
+                               int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
   return precision ? launch_pass1_f64(plan, a, grid, s) : launch_pass1_f32(plan, a, grid, s);
@@ -692,11 +742,11 @@ hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hi
   return precision ? launch_pass2_f64(plan, a, grid, s) : launch_pass2_f32(plan, a, grid, s);
 }
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                           const int32_t* part_j, int n, const int32_t* plan_tiles2, const int32_t* counts,
+                           const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
                            unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
-  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, plan_tiles2, counts, evaluated, fitness,
+  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, plan_parts2, counts, evaluated, fitness,
                                          argmax, s)
-                   : launch_finalize_f32(evals, segs, part_g, part_j, n, plan_tiles2, counts, evaluated, fitness,
+                   : launch_finalize_f32(evals, segs, part_g, part_j, n, plan_parts2, counts, evaluated, fitness,
                                          argmax, s);
 }
 }  // namespace fcas

@@ -35,6 +35,8 @@ struct SegDesc {
   int32_t k_lo, k_hi;   // inclusive in-band bins
   int32_t plan;         // FFT plan index
   int32_t registered;   // 1 once fcas_set_segment has completed
+  int32_t dk1;          // the plan's pass-1 register stride in bins (P1 N2)
+  int32_t reserved;
   double df;            // 1 / T
   double sigma[kMaxDet];
   int64_t j_lo, j_hi;   // coalescence samples searched: j_lo <= j < j_hi
@@ -47,6 +49,8 @@ struct EvalDesc {
   double q[kMaxDet][2];       // orthonormal basis of span(diag(sigma) U), FP64
   float qf[kMaxDet][2];       // same, rounded to float
   double v[kMaxDet][2];       // V = diag(sigma) U (kept for the gradient)
+  double step1[kMaxDet][2];   // exp(2 pi i dk1 dly_i): delay ramp across one pass-1 register stride
+  float step1f[kMaxDet][2];   // same, rounded to float
   int32_t seg;
   int32_t status;             // 1 evaluate, 0 outside the rectangle, -2 bad segment
   int32_t plan;
@@ -95,6 +99,15 @@ FCAS_HD void setup_one(const NetDesc& net, const SegDesc& sg, const double* th, 
   for (int i = 0; i < net.n_det; ++i) {
     const double* r = net.pos[i];
     ev.dly[i] = -(n[0] * r[0] + n[1] * r[1] + n[2] * r[2]) / kC * sg.df;
+    {
+      const double ps = (double)sg.dk1 * ev.dly[i];
+      double ss, cs;
+      sincos_rev(ps - rint(ps), &ss, &cs);
+      ev.step1[i][0] = cs;
+      ev.step1[i][1] = ss;
+      ev.step1f[i][0] = (float)cs;
+      ev.step1f[i][1] = (float)ss;
+    }
     double up = 0.0, uc = 0.0;
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) {
@@ -154,6 +167,14 @@ template <> struct Basis<float> {
 template <> struct Basis<double> {
   FCAS_HD static double get(const EvalDesc& e, int i, int m) { return e.q[i][m]; }
 };
+
+template <typename Real> FCAS_HD cplx<Real> ramp_step(const EvalDesc& e, int i);
+template <> FCAS_HD cplx<float> ramp_step<float>(const EvalDesc& e, int i) {
+  return mk<float>(e.step1f[i][0], e.step1f[i][1]);
+}
+template <> FCAS_HD cplx<double> ramp_step<double>(const EvalDesc& e, int i) {
+  return mk<double>(e.step1[i][0], e.step1[i][1]);
+}
 
 // W_0(k), W_1(k) for one in-band bin.  kk = k - k_lo.
 template <typename Real>
@@ -230,10 +251,13 @@ struct Plan {
   static constexpr int P1 = N1 / E1, P2 = N2 / E2;
   static constexpr int T1 = C * P1, T2 = RW * P2;           // threads per work item
   static constexpr int TILES1 = N2 / C, TILES2 = N1 / RW;   // work items per evaluation
+  static constexpr int DK1 = P1 * N2;                       // bin stride between a pass-1 thread's registers
+  static constexpr int PARTS2 = TILES2 * (T2 / 64);         // pass-2 partials (one per wavefront)
   static_assert(Rad1::product() == N1, "pass-1 radices must multiply to N1");
   static_assert(Rad2::product() == N2, "pass-2 radices must multiply to N2");
   static_assert(N1 % E1 == 0 && N2 % E2 == 0, "elements per thread must divide the length");
   static_assert(N2 % C == 0 && N1 % RW == 0, "tiles must divide the transform");
+  static_assert(T2 % 64 == 0 && 64 % P2 == 0, "pass-2 rows lie inside whole wavefronts");
 };
 
 // ---------------------------------------------------------------------------
@@ -247,7 +271,9 @@ struct Plan {
 // the delay ramps r_i(k) = exp(2 pi i k dly_i),
 //   W_m(k) = e_c(k) sum_i Q_im y^i_k r_i(k).
 // r_i is exact (FP64-reduced) at the thread's first bin and advanced by the
-// constant factor exp(2 pi i (P1 N2) dly_i) from register to register.
+// constant factor exp(2 pi i (P1 N2) dly_i) of the point's descriptor from
+// register to register.  Out-of-band registers read bin k_lo (any finite
+// value) and are cleared by a zero e_c, so no lane branches.
 // ---------------------------------------------------------------------------
 // Segment data one pass-1 thread needs for a work item: y of its in-band
 // registers and detectors, and the basis b of those bins (DT > 0 only).
@@ -263,7 +289,7 @@ struct Pass1Data {
 template <typename Real, class PL, int DT>
 FCAS_HD void pass1_fetch(Pass1Data<Real, PL, DT>& d, const SegDesc& sg, int tile, int c, int p) {
   constexpr int QH = PL::E1 / 2;
-  constexpr int DK = PL::P1 * PL::N2;
+  constexpr int DK = PL::DK1;
   static_assert(DT > 0, "prefetch needs a compile-time detector count");
   const int k2 = tile * PL::C + c;
   d.k0 = p * PL::N2 + k2;
@@ -279,11 +305,28 @@ FCAS_HD void pass1_fetch(Pass1Data<Real, PL, DT>& d, const SegDesc& sg, int tile
   }
 }
 
+// exp(2 pi i Phi) for an in-band bin with basis value b, 0 otherwise.
+template <typename Real>
+FCAS_HD cplx<Real> band_phase(const EvalDesc& ev, double b, bool in) {
+  const double ph = common_phase(ev.coef, b);
+  Real s, cc;
+  sincos_rev((Real)(ph - rint(ph)), &s, &cc);
+  return in ? mk<Real>(cc, s) : mk<Real>(0, 0);
+}
+
+// Delay ramp of detector i at the thread's first bin k0 (FP64 reduction).
+template <typename Real>
+FCAS_HD cplx<Real> first_ramp(const EvalDesc& ev, int i, int k0) {
+  const double ph0 = (double)k0 * ev.dly[i];
+  Real s, cc;
+  sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
+  return mk<Real>(cc, s);
+}
+
 // The prologue arithmetic on prefetched data (same results as pass1_prologue).
 template <typename Real, class PL, int DT>
 FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL, DT>& d, const EvalDesc& ev) {
   constexpr int QH = PL::E1 / 2;
-  constexpr int DK = PL::P1 * PL::N2;
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
     v[0][q] = mk<Real>(0, 0);
@@ -291,33 +334,22 @@ FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL,
   }
 #pragma unroll
   for (int i = 0; i < DT; ++i) {
-    const double ph0 = (double)d.k0 * ev.dly[i], phs = (double)DK * ev.dly[i];
-    Real s, cc;
-    sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
-    cplx<Real> ramp = mk<Real>(cc, s);
-    sincos_rev((Real)(phs - rint(phs)), &s, &cc);
-    const cplx<Real> step = mk<Real>(cc, s);
+    cplx<Real> ramp = first_ramp<Real>(ev, i, d.k0);
+    const cplx<Real> step = ramp_step<Real>(ev, i);
     const Real q0 = Basis<Real>::get(ev, i, 0), q1 = Basis<Real>::get(ev, i, 1);
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
-      if (d.in[q]) {
-        const cplx<Real> u = mul(d.y[i][q], ramp);
-        v[0][q] = mk<Real>(v[0][q].x + q0 * u.x, v[0][q].y + q0 * u.y);
-        v[1][q] = mk<Real>(v[1][q].x + q1 * u.x, v[1][q].y + q1 * u.y);
-      }
-      ramp = mul(ramp, step);
+      const cplx<Real> u = mul(d.y[i][q], ramp);
+      v[0][q] = mk<Real>(v[0][q].x + q0 * u.x, v[0][q].y + q0 * u.y);
+      v[1][q] = mk<Real>(v[1][q].x + q1 * u.x, v[1][q].y + q1 * u.y);
+      if (q + 1 < QH) ramp = mul(ramp, step);
     }
   }
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
-    if (d.in[q]) {
-      const double ph = common_phase(ev.coef, d.b[q]);
-      Real s, cc;
-      sincos_rev((Real)(ph - rint(ph)), &s, &cc);
-      const cplx<Real> e = mk<Real>(cc, s);
-      v[0][q] = mul(v[0][q], e);
-      v[1][q] = mul(v[1][q], e);
-    }
+    const cplx<Real> e = band_phase<Real>(ev, d.b[q], d.in[q]);
+    v[0][q] = mul(v[0][q], e);
+    v[1][q] = mul(v[1][q], e);
   }
 }
 
@@ -327,50 +359,40 @@ template <typename Real, class PL, int DT = 0>
 FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDesc& sg, int n_det_rt,
                             int tile, int c, int p) {
   constexpr int QH = PL::E1 / 2;
-  constexpr int DK = PL::P1 * PL::N2;
+  constexpr int DK = PL::DK1;
   const int n_det = DT > 0 ? DT : n_det_rt;
   const int k2 = tile * PL::C + c;
   const int k0 = p * PL::N2 + k2;
   const cplx<Real>* y = (const cplx<Real>*)sg.y;
   bool in[QH];
+  int kk[QH];
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
     const int k = k0 + q * DK;
     in[q] = (k >= sg.k_lo) && (k <= sg.k_hi);
+    kk[q] = in[q] ? k - sg.k_lo : 0;
     v[0][q] = mk<Real>(0, 0);
     v[1][q] = mk<Real>(0, 0);
   }
 #pragma unroll
   for (int i = 0; i < (DT > 0 ? DT : kMaxDet); ++i) {
     if (DT == 0 && i >= n_det) break;
-    const double ph0 = (double)k0 * ev.dly[i], phs = (double)DK * ev.dly[i];
-    Real s, cc;
-    sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
-    cplx<Real> ramp = mk<Real>(cc, s);
-    sincos_rev((Real)(phs - rint(phs)), &s, &cc);
-    const cplx<Real> step = mk<Real>(cc, s);
+    cplx<Real> ramp = first_ramp<Real>(ev, i, k0);
+    const cplx<Real> step = ramp_step<Real>(ev, i);
     const Real q0 = Basis<Real>::get(ev, i, 0), q1 = Basis<Real>::get(ev, i, 1);
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
-      if (in[q]) {
-        const int kk = k0 + q * DK - sg.k_lo;
-        const cplx<Real> u = mul(y[(int64_t)kk * n_det + i], ramp);
-        v[0][q] = mk<Real>(v[0][q].x + q0 * u.x, v[0][q].y + q0 * u.y);
-        v[1][q] = mk<Real>(v[1][q].x + q1 * u.x, v[1][q].y + q1 * u.y);
-      }
-      ramp = mul(ramp, step);
+      const cplx<Real> u = mul(y[(int64_t)kk[q] * n_det + i], ramp);
+      v[0][q] = mk<Real>(v[0][q].x + q0 * u.x, v[0][q].y + q0 * u.y);
+      v[1][q] = mk<Real>(v[1][q].x + q1 * u.x, v[1][q].y + q1 * u.y);
+      if (q + 1 < QH) ramp = mul(ramp, step);
     }
   }
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
-    if (in[q]) {
-      const double ph = common_phase(ev.coef, sg.b[k0 + q * DK - sg.k_lo]);
-      Real s, cc;
-      sincos_rev((Real)(ph - rint(ph)), &s, &cc);
-      const cplx<Real> e = mk<Real>(cc, s);
-      v[0][q] = mul(v[0][q], e);
-      v[1][q] = mul(v[1][q], e);
-    }
+    const cplx<Real> e = band_phase<Real>(ev, sg.b[kk[q]], in[q]);
+    v[0][q] = mul(v[0][q], e);
+    v[1][q] = mul(v[1][q], e);
   }
 }
 
@@ -403,15 +425,18 @@ FCAS_HD void pass2_fetch(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int
   }
 }
 
+// w_N^{k2 j1} for k2 = p + q P2: exact (one sine/cosine pair) at q = 0, then
+// advanced by the factor w_N^{P2 j1} from register to register.
 template <typename Real, class PL>
 FCAS_HD void pass2_twiddle(cplx<Real> (&v)[2][PL::E2], int tile, int r, int p) {
   const int j1 = tile * PL::RW + r;
+  cplx<Real> t = twiddle<Real>(p * j1, (int)PL::N);                // p j1 < N
+  const cplx<Real> st = twiddle<Real>(PL::P2 * j1, (int)PL::N);    // P2 j1 < N
 #pragma unroll
   for (int q = 0; q < PL::E2; ++q) {
-    const int k2 = p + q * PL::P2;
-    const cplx<Real> t = twiddle<Real>(k2 * j1, (int)PL::N);   // k2 j1 < N: no reduction needed
     v[0][q] = mul(v[0][q], t);
     v[1][q] = mul(v[1][q], t);
+    if (q + 1 < PL::E2) t = mul(t, st);
   }
 }
 
@@ -428,15 +453,28 @@ template <typename Real, class PL>
 FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p, Real& best, int& best_j,
                         int64_t j_lo = 0, int64_t j_hi = PL::N) {
   const int j1 = tile * PL::RW + r;
+  const int lo = j_lo > 0 ? (int)j_lo : 0;
+  const int hi = j_hi < PL::N ? (int)j_hi : (int)PL::N;
   best = (Real)-1;
   best_j = 0x7fffffff;
+  if (lo == 0 && hi == (int)PL::N) {   // whole series (uniform branch)
 #pragma unroll
-  for (int q = 0; q < PL::E2; ++q) {
-    const Real g = norm2(v[0][q]) + norm2(v[1][q]);
-    const int j = j1 + PL::N1 * (p + q * PL::P2);
-    if (g > best && j >= j_lo && j < j_hi) {   // j grows with q: ties keep the smaller j
-      best = g;
-      best_j = j;
+    for (int q = 0; q < PL::E2; ++q) {
+      const Real g = norm2(v[0][q]) + norm2(v[1][q]);
+      if (g > best) {   // j grows with q: ties keep the smaller j
+        best = g;
+        best_j = j1 + PL::N1 * (p + q * PL::P2);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PL::E2; ++q) {
+      const Real g = norm2(v[0][q]) + norm2(v[1][q]);
+      const int j = j1 + PL::N1 * (p + q * PL::P2);
+      if (g > best && j >= lo && j < hi) {
+        best = g;
+        best_j = j;
+      }
     }
   }
 }

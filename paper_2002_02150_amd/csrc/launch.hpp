@@ -11,7 +11,7 @@ namespace fcas {
 
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
 hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* theta, const int32_t* seg_ids,
-                        int n, EvalDesc* evals, int32_t* lists, int32_t* counts, int list_stride,
+                        int n, EvalDesc* evals, int32_t* lists, int32_t* counts, int list_stride, int build_lists,
                         int32_t* err, hipStream_t s);
 
 // fused persistent schedule (float plans)
@@ -22,7 +22,7 @@ int fused_blocks_per_cu(int plan);
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                           const int32_t* part_j, int n, const int32_t* plan_tiles2, const int32_t* counts,
+                           const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
                            unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s);
 
 // segment preparation: sigma_i^2 = 4 df sum_B f^-7/3 / S, y = 4 df x f^-7/6 / (S sigma), b = (f/f*)^-1/3

@@ -10,7 +10,9 @@
 
 namespace fcas {
 
-constexpr int kMaxTiles2 = 128;   // largest N1 / RW over all plans
+// Pass 2 leaves one partial (maximum, sample) per wavefront of each work item:
+// TILES2 * T2 / 64 per evaluation, at most N1 * P2 / 64 = 512 over all plans.
+constexpr int kMaxParts2 = 512;
 
 template <int... R>
 using Rad = Radices<R...>;
@@ -47,7 +49,7 @@ using Rad = Radices<R...>;
   using PlanF##id = Plan<n1, e1, Rad<FCAS_UNPAREN r1>, cf, n2, e2, Rad<FCAS_UNPAREN r2>, rwf>; \
   using PlanD##id = Plan<n1, e1, Rad<FCAS_UNPAREN r1>, cd, n2, e2, Rad<FCAS_UNPAREN r2>, rwd>; \
   static_assert(PlanF##id::N == n && PlanD##id::N == n, "plan length");                    \
-  static_assert(PlanF##id::TILES2 <= kMaxTiles2 && PlanD##id::TILES2 <= kMaxTiles2, "tiles");
+  static_assert(PlanF##id::PARTS2 <= kMaxParts2 && PlanD##id::PARTS2 <= kMaxParts2, "pass-2 partials");
 
 FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
 
@@ -58,12 +60,14 @@ struct PlanInfo {
   int n1, n2, e1, e2;
   int cols[2], rows[2];       // [precision]: 0 float, 1 double
   int tiles1[2], tiles2[2];
+  int parts2[2];              // pass-2 partials per evaluation
   int threads1[2], threads2[2];
 };
 
 #define FCAS_PLAN_INFO(id, n, n1, e1, r1, cf, cd, n2, e2, r2, rwf, rwd)                       \
   {n, n1, n2, e1, e2, {cf, cd}, {rwf, rwd},                                                   \
    {PlanF##id::TILES1, PlanD##id::TILES1}, {PlanF##id::TILES2, PlanD##id::TILES2},           \
+   {PlanF##id::PARTS2, PlanD##id::PARTS2},                                                   \
    {PlanF##id::T1, PlanD##id::T1}, {PlanF##id::T2, PlanD##id::T2}},
 
 inline const PlanInfo kPlans[kNumPlans] = {FCAS_PLAN_LIST(FCAS_PLAN_INFO)};

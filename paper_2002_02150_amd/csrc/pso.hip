@@ -65,7 +65,10 @@ __global__ void k_pso_init(PsoDev p, double* __restrict__ theta) {
     p.best_f[r] = -INFINITY;
     p.best_j[r] = -1;
     for (int d = 0; d < 4; ++d) p.best_x[4 * r + d] = 0.0;
-    if (r == 0) p.iteration[0] = 0;
+    if (r == 0) {
+      p.iteration[0] = 0;
+      p.iteration[1] = 0;
+    }
   }
 }
 
@@ -99,32 +102,39 @@ __global__ void k_pso_step(PsoDev p, const double* __restrict__ fitness, const i
       for (int d = 0; d < 4; ++d) p.best_x[4 * r + d] = p.pbest_x[4 * (base + b) + d];
     }
   }
-  if (i >= P) return;
-  const int cand[3] = {(i + P - 1) % P, i, (i + 1) % P};
-  int lb = cand[0];
-  for (int c = 1; c < 3; ++c)
-    if (pf[cand[c]] > pf[lb]) lb = cand[c];
-  const double w = p.n_iter <= 1 ? p.w0 : p.w0 - (p.w0 - p.w1) * ((double)iter / (double)(p.n_iter - 1));
-  double r1[4], r2[4];
-  uniforms4(p.seed, (uint32_t)(iter + 1), i, r, 2, r1);
-  uniforms4(p.seed, (uint32_t)(iter + 1), i, r, 3, r2);
-  const int64_t o = base + i, ol = base + lb;
-  for (int d = 0; d < 4; ++d) {
-    const double xv = p.x[4 * o + d];
-    const double t0 = w * p.v[4 * o + d];
-    const double t1 = (p.c1 * r1[d]) * (p.pbest_x[4 * o + d] - xv);
-    const double t2 = (p.c2 * r2[d]) * (p.pbest_x[4 * ol + d] - xv);
-    const double vn = clampv((t0 + t1) + t2, p.vmax);
-    const double xn = xv + vn;
-    p.v[4 * o + d] = vn;
-    p.x[4 * o + d] = xn;
-    theta[4 * o + d] = p.lo[d] + xn * p.span[d];
+  if (i < P) {
+    const int cand[3] = {(i + P - 1) % P, i, (i + 1) % P};
+    int lb = cand[0];
+    for (int c = 1; c < 3; ++c)
+      if (pf[cand[c]] > pf[lb]) lb = cand[c];
+    const double w = p.n_iter <= 1 ? p.w0 : p.w0 - (p.w0 - p.w1) * ((double)iter / (double)(p.n_iter - 1));
+    double r1[4], r2[4];
+    uniforms4(p.seed, (uint32_t)(iter + 1), i, r, 2, r1);
+    uniforms4(p.seed, (uint32_t)(iter + 1), i, r, 3, r2);
+    const int64_t o = base + i, ol = base + lb;
+    for (int d = 0; d < 4; ++d) {
+      const double xv = p.x[4 * o + d];
+      const double t0 = w * p.v[4 * o + d];
+      const double t1 = (p.c1 * r1[d]) * (p.pbest_x[4 * o + d] - xv);
+      const double t2 = (p.c2 * r2[d]) * (p.pbest_x[4 * ol + d] - xv);
+      const double vn = clampv((t0 + t1) + t2, p.vmax);
+      const double xn = xv + vn;
+      p.v[4 * o + d] = vn;
+      p.x[4 * o + d] = xn;
+      theta[4 * o + d] = p.lo[d] + xn * p.span[d];
+    }
   }
-}
-
-// advances the device iteration counter once every run has read it
-__global__ void k_pso_tick(int32_t* iteration) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) iteration[0] += 1;
+  // The iteration count advances once every run has read it: each run's
+  // work-group counts itself in iteration[1] (a device-scope atomic), and the
+  // last one stores count + 1 and clears the tally.
+  __syncthreads();
+  if (i == 0) {
+    const int done = __hip_atomic_fetch_add(p.iteration + 1, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (done == (int)gridDim.x - 1) {
+      __hip_atomic_store(p.iteration + 1, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(p.iteration, iter + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
 }
 
 __global__ void k_pso_best(PsoDev p, double* out_f, double* out_theta, int32_t* out_j, int32_t* out_run) {
@@ -150,9 +160,6 @@ hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t
                            hipStream_t s) {
   hipLaunchKernelGGL(k_pso_step, dim3(p.n_runs), dim3(block_for(p.n_particles)),
                      sizeof(double) * p.n_particles, s, p, fitness, argmax, theta_next);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_pso_tick, dim3(1), dim3(64), 0, s, p.iteration);
   return hipGetLastError();
 }
 

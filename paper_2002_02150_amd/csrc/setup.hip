@@ -9,38 +9,54 @@ __global__ void k_zero_i32(int32_t* p, int n) {
 }
 
 // One thread per point: status, plan list entry, and the FP64 set-up.
+// With build_lists = 0 only the descriptors are refreshed (the work lists and
+// their counts are left alone).  List entries of one wavefront that share a
+// plan are appended with a single atomic.
 __global__ void k_setup(const NetDesc* __restrict__ netp, const SegDesc* __restrict__ segs,
                         const double* __restrict__ theta, const int32_t* __restrict__ seg_ids, int n,
                         EvalDesc* __restrict__ evals, int32_t* __restrict__ lists, int32_t* __restrict__ counts,
-                        int list_stride, int32_t* __restrict__ err) {
+                        int list_stride, int build_lists, int32_t* __restrict__ err) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  const int lane = threadIdx.x & 63;
   const NetDesc& net = *netp;
-  EvalDesc& ev = evals[e];
-  const int s = seg_ids[e];
-  ev.seg = s;
-  if (s < 0 || s >= net.max_segments || !segs[s].registered) {
-    ev.status = -2;
-    ev.plan = 0;
-    atomicOr(err, 1);
-    return;
+  int plan = -1;   // plan of a point to append to its list, else -1
+  if (e < n) {
+    EvalDesc& ev = evals[e];
+    const int s = seg_ids[e];
+    ev.seg = s;
+    if (s < 0 || s >= net.max_segments || !segs[s].registered) {
+      ev.status = -2;
+      ev.plan = 0;
+      atomicOr(err, 1);
+    } else {
+      const SegDesc& sg = segs[s];
+      ev.plan = sg.plan;
+      const double* th = theta + 4 * (int64_t)e;
+      bool inside = true;
+      for (int d = 0; d < 4; ++d) {
+        const double t = th[d];
+        inside = inside && isfinite(t) && t >= net.box_lo[d] && t <= net.box_hi[d];
+      }
+      if (!inside) {
+        ev.status = 0;
+      } else {
+        setup_one(net, sg, th, ev);
+        ev.status = 1;
+        if (build_lists) plan = sg.plan;
+      }
+    }
   }
-  const SegDesc& sg = segs[s];
-  ev.plan = sg.plan;
-  const double* th = theta + 4 * (int64_t)e;
-  bool inside = true;
-  for (int d = 0; d < 4; ++d) {
-    const double t = th[d];
-    inside = inside && isfinite(t) && t >= net.box_lo[d] && t <= net.box_hi[d];
+  unsigned long long todo = __ballot(plan >= 0);
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const int lp = __shfl(plan, leader, 64);
+    const unsigned long long same = __ballot(plan == lp);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counts + lp, __popcll(same));
+    base = __shfl(base, leader, 64);
+    if (plan == lp) lists[(int64_t)lp * list_stride + base + __popcll(same & ((1ull << lane) - 1))] = e;
+    todo &= ~same;
   }
-  if (!inside) {
-    ev.status = 0;
-    return;
-  }
-  setup_one(net, sg, th, ev);
-  ev.status = 1;
-  const int pos = atomicAdd(counts + sg.plan, 1);
-  lists[(int64_t)sg.plan * list_stride + pos] = e;
 }
 
 // sigma_i^2 = 4 df sum_{k in B} f_k^(-7/3) / S^i_k  (template norm, Sec. II.D).
@@ -90,11 +106,11 @@ hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s) {
 }
 
 hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* theta, const int32_t* seg_ids,
-                        int n, EvalDesc* evals, int32_t* lists, int32_t* counts, int list_stride,
+                        int n, EvalDesc* evals, int32_t* lists, int32_t* counts, int list_stride, int build_lists,
                         int32_t* err, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_setup, dim3((n + 127) / 128), dim3(128), 0, s, net, segs, theta, seg_ids, n, evals, lists,
-                     counts, list_stride, err);
+  hipLaunchKernelGGL(k_setup, dim3((n + 63) / 64), dim3(64), 0, s, net, segs, theta, seg_ids, n, evals, lists,
+                     counts, list_stride, build_lists, err);
   return hipGetLastError();
 }
 

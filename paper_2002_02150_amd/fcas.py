@@ -21,6 +21,7 @@ MIXED = 0
 FP64 = 1
 SCHEDULE_FUSED = 0
 SCHEDULE_TWO_PASS = 1
+SCHEDULE_TWO_STREAMS = 2
 MAX_DET = 8
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP", -5: "ENOMEM", -6: "ECAPACITY"}
@@ -320,7 +321,8 @@ class Swarm:
         self.best_x = torch.zeros(R, 4, **f64)
         self.best_f = torch.zeros(R, **f64)
         self.best_j = torch.zeros(R, dtype=torch.int32, device=dev)
-        self.iteration = torch.zeros(1, dtype=torch.int32, device=dev)
+        self._iter = torch.zeros(2, dtype=torch.int32, device=dev)   # count, and pso_step's tally
+        self.iteration = self._iter[:1]
         self.theta = torch.zeros(R * P, 4, **f64)
         self.out_f = torch.zeros(1, **f64)
         self.out_theta = torch.zeros(4, **f64)
@@ -328,7 +330,7 @@ class Swarm:
         self.out_run = torch.zeros(1, dtype=torch.int32, device=dev)
         self._p = cfg._c()
         self._s = _PsoState(*[t.data_ptr() for t in (self.x, self.v, self.pbest_x, self.pbest_f, self.pbest_j,
-                                                      self.best_x, self.best_f, self.best_j, self.iteration)])
+                                                      self.best_x, self.best_f, self.best_j, self._iter)])
 
     @property
     def n(self):

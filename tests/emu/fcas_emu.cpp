@@ -143,6 +143,7 @@ static int main_t(int plan, int n_det, int k_lo, int k_hi, double df, double f_s
   sg.k_hi = k_hi;
   sg.plan = plan;
   sg.registered = 1;
+  sg.dk1 = (int32_t)(kPlans[plan].n / kPlans[plan].e1);
   sg.df = df;
   for (int i = 0; i < n_det; ++i) sg.sigma[i] = sig[i];
   EvalDesc ev{};
