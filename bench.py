@@ -40,8 +40,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=320)
-    ap.add_argument("--schedule", choices=("fused", "two-pass", "two-streams"), default="two-pass",
-                    help="schedule of the timed search; its kernel-timing region runs the two-stream schedule as two-pass")
+    ap.add_argument("--schedule", choices=("fused", "two-pass"), default="two-pass")
     ap.add_argument("--config", choices=("search", "batched", "gradient"), default="search",
                     help="search: the benchmark configuration (default); batched: 256 ragged segments, "
                          "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source")
@@ -59,12 +58,7 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-SCHEDULES = {"fused": 0, "two-pass": 1, "two-streams": 2}
-
-
-def synth_box():
-    import synth
-    return synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+SCHEDULES = {"fused": 0, "two-pass": 1}
 
 
 def make_workload(torch, dev, schedule):
@@ -106,11 +100,10 @@ class Search:
         self.pol_j = torch.empty(1, dtype=torch.int32, device=dev)
         self.graph = None
 
-    def iteration(self, timed=False, ctx=None):
-        ctx = ctx or self.ctx
-        ctx.set_timing(timed)   # kernel events bracket only the fitness launches
-        ctx.eval(self.sw.theta, self.seg, self.f, self.j)
-        ctx.set_timing(False)
+    def iteration(self, timed=False):
+        self.ctx.set_timing(timed)   # kernel events bracket only the fitness launches
+        self.ctx.eval(self.sw.theta, self.seg, self.f, self.j)
+        self.ctx.set_timing(False)
         self.sw.step(self.f, self.j)
         self.sw.best()
 
@@ -360,36 +353,24 @@ def main():
     dt = time.perf_counter() - t
     ev1 = ctx.evaluated()
     iterations_done = sw.iteration.item()
-    # timed region 2: K iterations launched eagerly on one stream (two-pass or
-    # fused schedule, so that each FFT kernel runs alone), HIP events around the
-    # FFT passes
-    kctx = ctx
-    if a.schedule == "two-streams":
-        from paper_2002_02150_amd import Context
-        kctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=synth_box()[0],
-                                    box_hi=synth_box()[1], max_batch=RUNS * PARTICLES, max_samples=N_SAMPLES,
-                                    schedule=SCHEDULES["two-pass"])
-        kctx.set_segment(0, xf, psd_d)
-        search.iteration(ctx=kctx)
-        torch.cuda.synchronize()
-    ev2 = kctx.evaluated()
+    # timed region 2: K iterations launched eagerly, HIP events around the FFT
+    # passes
+    ev2 = ctx.evaluated()
     t2 = time.perf_counter()
     per_launch = []
     prev = ev2
     for _ in range(a.steps):
-        search.iteration(timed=True, ctx=kctx)
+        search.iteration(timed=True)
         if a.launch_counts:      # synchronises every step: only for pairing with counter runs
-            cur = kctx.evaluated()
+            cur = ctx.evaluated()
             per_launch.append(cur - prev)
             prev = cur
     torch.cuda.synchronize()
     dt2 = time.perf_counter() - t2
-    ev3 = kctx.evaluated()
-    ms1, n1 = kctx.read_timing("pass1")
-    ms2, n2 = kctx.read_timing("pass2")
-    msf, nf = kctx.read_timing("fused")
-    if kctx is not ctx:
-        kctx.close()
+    ev3 = ctx.evaluated()
+    ms1, n1 = ctx.read_timing("pass1")
+    ms2, n2 = ctx.read_timing("pass2")
+    msf, nf = ctx.read_timing("fused")
     evals = a.steps * RUNS * PARTICLES
     # value counts the fitness evaluations performed for the particles inside the
     # rectangle (points that flew out are not evaluated); the polish is timed but

@@ -54,16 +54,11 @@ extern "C" {
                          projection and maximum in FP32                           */
 #define FCAS_FP64 1   /* everything in FP64 (the plain reference path)            */
 
-/* launch schedule of the two FFT passes (FUSED: FCAS_MIXED only) */
+/* launch schedule of the two FFT passes (FUSED: FCAS_MIXED only; an FCAS_FP64
+ * context runs TWO_PASS) */
 #define FCAS_SCHEDULE_FUSED 0     /* one persistent launch per plan, passes pipelined  */
-#define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk  */
-#define FCAS_SCHEDULE_TWO_STREAMS 2 /* two-pass, with the points of a batch that fits
-                                     the workspace split in two halves whose launches
-                                     run on the caller's stream and on a second,
-                                     library-owned stream (forked from and joined back
-                                     into the caller's stream by events, so the call
-                                     stays capturable into a HIP graph); the halves
-                                     overlap on the device                          */
+#define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk
+                                     (the faster one on MI355X: recommended)          */
 
 typedef struct fcas_ctx fcas_ctx;
 
@@ -87,7 +82,7 @@ typedef struct {
   int32_t precision;      /* FCAS_MIXED or FCAS_FP64 */
   int32_t max_batch;      /* largest n accepted by fitness_eval/grad_batch */
   int32_t max_segments;   /* segment ids are 0..max_segments-1 */
-  int32_t schedule;       /* FCAS_SCHEDULE_TWO_PASS, _TWO_STREAMS or _FUSED */
+  int32_t schedule;       /* FCAS_SCHEDULE_TWO_PASS or FCAS_SCHEDULE_FUSED */
   int64_t max_samples;    /* largest segment length N that will be registered */
   int64_t workspace_bytes;/* FFT workspace; 0 = enough for max_batch evaluations
                              of max_samples (batches beyond it run in chunks) */
@@ -120,7 +115,8 @@ int fcas_plan_info(int32_t plan, int64_t* n_samples, int32_t* n1, int32_t* n2, i
 
 /* Use plan `plan` for segments of its length registered after this call, with
  * grid1 / grid2 persistent work-groups for its two passes (0 = default).
- * This is how the autotuner's choice is applied. */
+ * This is how the autotuner's choice is applied.  FCAS_EINVAL for a plan out
+ * of range or grid sizes outside [0, 2^20]. */
 int fcas_select_plan(fcas_ctx* ctx, int32_t plan, int32_t grid1, int32_t grid2);
 
 /* Registers (or replaces) segment `seg_id` of n_samples samples per detector

@@ -5,8 +5,8 @@ fastest choice per length to tuning.json (applied by Context by default).
     python -m paper_2002_02150_amd.autotune [--lengths 131072,262144] [--out PATH]
 
 Timing: fitness batches of `batch` points spread over the search rectangle
-(every point evaluated), HIP events around the two pass kernels, median over
-repetitions.  The data are random: the cost of an evaluation does not depend
+(every point evaluated), HIP events around `reps` back-to-back calls, best of
+three such runs.  The data are random: the cost of an evaluation does not depend
 on the data values.
 """
 from __future__ import annotations
@@ -15,7 +15,6 @@ import argparse
 import json
 import math
 import os
-import statistics
 import sys
 import time
 
@@ -24,7 +23,7 @@ import torch
 from . import fcas
 
 DEFAULT_LENGTHS = (8192, 65536, 131072, 196608, 262144)
-GRIDS = (512, 1024, 2048, 4096)
+GRIDS = (1024, 2048, 4096)
 # rectangle of component masses in [1, 3] Msun at f_low = 30 Hz
 BOX_LO = (0.0, -math.pi / 2, 15.0336, 0.841913)
 BOX_HI = (2.0 * math.pi, math.pi / 2, 93.8141, 1.75126)
@@ -47,25 +46,26 @@ def _network(n_det, device):
 
 
 def time_plan(ctx, plan, g1, g2, xf, psd, theta, seg, reps):
+    """Mean device time (ms) of one fitness call, over `reps` back-to-back calls."""
     ctx.select_plan(plan, g1, g2)
     ctx.set_segment(0, xf, psd)
     f = torch.empty(theta.shape[0], dtype=torch.float64, device=ctx.device)
     j = torch.empty(theta.shape[0], dtype=torch.int32, device=ctx.device)
     for _ in range(3):
         ctx.eval(theta, seg, f, j)
-    torch.cuda.synchronize(ctx.device)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     samples = []
-    for _ in range(reps):
-        ctx.set_timing(True)
-        ctx.eval(theta, seg, f, j)
-        ctx.set_timing(False)
-        m1, _ = ctx.read_timing("pass1")
-        m2, _ = ctx.read_timing("pass2")
-        samples.append(m1 + m2)
-    return statistics.median(samples)
+    for _ in range(3):
+        e0.record()
+        for _ in range(reps):
+            ctx.eval(theta, seg, f, j)
+        e1.record()
+        torch.cuda.synchronize(ctx.device)
+        samples.append(e0.elapsed_time(e1) / reps)
+    return min(samples)
 
 
-def autotune(lengths=DEFAULT_LENGTHS, n_det=4, fs=2048.0, batch=320, reps=15, grids=GRIDS, out=fcas.TUNING_PATH,
+def autotune(lengths=DEFAULT_LENGTHS, n_det=4, fs=2048.0, batch=320, reps=10, grids=GRIDS, out=fcas.TUNING_PATH,
              device=0, log=print):
     dev = torch.device("cuda", device)
     pos, ten = _network(n_det, dev)
@@ -98,6 +98,7 @@ def autotune(lengths=DEFAULT_LENGTHS, n_det=4, fs=2048.0, batch=320, reps=15, gr
         choices[str(n)] = best
         log(f"N={n}: chose {best}")
     doc = dict(device=torch.cuda.get_device_name(dev), n_det=n_det, batch=batch, reps=reps,
+               what="mean device time of one fitness call (set-up, passes, finalize)",
                written=time.strftime("%Y-%m-%d %H:%M:%S"), choices=choices, measurements=results)
     if out:
         with open(out, "w") as fh:
@@ -110,7 +111,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--lengths", default=",".join(str(n) for n in DEFAULT_LENGTHS))
     ap.add_argument("--out", default=fcas.TUNING_PATH)
-    ap.add_argument("--reps", type=int, default=15)
+    ap.add_argument("--reps", type=int, default=10)
     a = ap.parse_args(argv)
     autotune(tuple(int(x) for x in a.lengths.split(",")), reps=a.reps, out=a.out,
              log=lambda s: print(s, flush=True))

@@ -18,30 +18,16 @@ struct PassArgs {
   void* part_g;            // [max_batch][kMaxParts2] partial maxima (Real)
   int32_t* part_j;         // [max_batch][kMaxParts2] their samples
   int32_t n_det;
-  int32_t chunk_begin;     // first list position of this chunk
-  int32_t cap;             // workspace slots (positions per chunk)
-  int32_t split_part;      // this launch takes share split_part of split_parts of the chunk
-  int32_t split_parts;     // (1: the whole chunk)
+  int32_t chunk_begin;     // first list position handled by this launch
+  int32_t cap;             // workspace slots (positions per launch)
 };
 
-// Narrows `a` to the list positions one launch handles: the chunk
-// [chunk_begin, chunk_begin + cap) of the plan's list, and within it share
-// split_part of split_parts near-equal shares (sized from the count the set-up
-// kernel wrote, so both passes of a share agree).  Moves chunk_begin and ws to
-// the share's first position and returns the number of positions.
-template <typename Real, class PL>
-__device__ __forceinline__ int launch_span(PassArgs& a) {
-  int cnt = *a.count - a.chunk_begin;
-  cnt = cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
-  if (a.split_parts > 1) {
-    const int per = (cnt + a.split_parts - 1) / a.split_parts;
-    const int first = a.split_part * per;
-    cnt -= first;
-    cnt = cnt < 0 ? 0 : (cnt > per ? per : cnt);
-    a.chunk_begin += first;
-    a.ws = (cplx<Real>*)a.ws + (int64_t)first * 2 * PL::N;
-  }
-  return cnt;
+// Number of list positions one launch handles: the chunk [chunk_begin,
+// chunk_begin + cap) of the plan's list, cut to the count the set-up kernel
+// wrote.
+__device__ __forceinline__ int launch_span(const PassArgs& a) {
+  const int cnt = *a.count - a.chunk_begin;
+  return cnt < 0 ? 0 : (cnt > a.cap ? a.cap : cnt);
 }
 
 // ---------------------------------------------------------------------------
@@ -112,44 +98,45 @@ __device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, con
   pass1_fetch<Real, PL, DT>(d, a.segs[ev.seg], item - slot * PL::TILES1, c, p);
 }
 
-template <typename Real, class PL, int DT>
-__device__ __forceinline__ void pass1_item(const Pass1Data<Real, PL, DT>& d, const PassArgs& a, int item, int c,
-                                           int p, cplx<Real>* buf0, cplx<Real>* buf1, const cplx<Real>* tw) {
-  const int slot = item / PL::TILES1;
-  const int tile = item - slot * PL::TILES1;
-  const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
-  cplx<Real> v[2][PL::E1];
-  pass1_compute<Real, PL, DT>(v, d, ev);
-  run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
-  pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
-}
+// LDS of the two passes: exchange buffers and twiddle tables.
+template <typename Real, class PL>
+struct PassLds {
+  static constexpr int LP1 = lds_padded_len(PL::N1), LP2 = lds_padded_len(PL::N2);
+  static constexpr int X1 = kLdsSeries<Real> * PL::C * LP1, X2 = kLdsSeries<Real> * PL::RW * LP2;
+  static constexpr int X = X1 > X2 ? X1 : X2;
+  static constexpr int TW = PL::N1 > PL::N2 ? PL::N1 : PL::N2;
+};
 
+// Pass 1 on the items of `a` taken by work-group `block` of `nblocks`
+// (tw holds the length-N1 twiddles).
 template <typename Real, class PL, int DT>
-__global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))) k_pass1(PassArgs a) {
-  constexpr int LP = lds_padded_len(PL::N1);
-  __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::C * LP];
-  __shared__ cplx<Real> tw[PL::N1];
+__device__ __forceinline__ void pass1_body(PassArgs a, cplx<Real>* lds, const cplx<Real>* tw, int block,
+                                           int nblocks) {
+  constexpr int LP = PassLds<Real, PL>::LP1;
   const int tid = threadIdx.x;
-  for (int m = tid; m < PL::N1; m += PL::T1) tw[m] = twiddle<Real>(m, PL::N1);
-  __syncthreads();
-  const int items = launch_span<Real, PL>(a) * PL::TILES1;
+  const int items = launch_span(a) * PL::TILES1;
   const int c = tid % PL::C, p = tid / PL::C;
   cplx<Real>* buf0 = lds + c * LP;
   cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::C + c) * LP : buf0;
   if constexpr (DT > 0) {
-    // software pipeline: the segment data of the next item are fetched while
-    // this one is transformed
-    Pass1Data<Real, PL, DT> nxt;
-    int item = blockIdx.x;
-    if (item < items) pass1_fetch_item<Real, PL, DT>(nxt, a, item, c, p);
-    for (; item < items; item += gridDim.x) {
-      const Pass1Data<Real, PL, DT> cur = nxt;
-      const int next = item + gridDim.x;
-      if (next < items) pass1_fetch_item<Real, PL, DT>(nxt, a, next, c, p);
-      pass1_item<Real, PL, DT>(cur, a, item, c, p, buf0, buf1, tw);
+    // software pipeline: once an item's prologue has consumed its segment
+    // data, the next item's are fetched while this one is transformed (one set
+    // of prefetch registers)
+    Pass1Data<Real, PL, DT> d;
+    int item = block;
+    if (item < items) pass1_fetch_item<Real, PL, DT>(d, a, item, c, p);
+    for (; item < items; item += nblocks) {
+      const int slot = item / PL::TILES1;
+      const int tile = item - slot * PL::TILES1;
+      cplx<Real> v[2][PL::E1];
+      pass1_compute<Real, PL, DT>(v, d, a.evals[a.list[a.chunk_begin + slot]]);
+      const int next = item + nblocks;
+      if (next < items) pass1_fetch_item<Real, PL, DT>(d, a, next, c, p);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
+      pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
     }
   } else {
-    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+    for (int item = block; item < items; item += nblocks) {
       const int slot = item / PL::TILES1;
       const int tile = item - slot * PL::TILES1;
       const int e = a.list[a.chunk_begin + slot];
@@ -162,6 +149,20 @@ __global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))
       pass1_store<Real, PL>(v, ws, tile, c, p);
     }
   }
+}
+
+template <typename Real, int L, int T>
+__device__ __forceinline__ void init_twiddles(cplx<Real>* tw) {
+  for (int m = threadIdx.x; m < L; m += T) tw[m] = twiddle<Real>(m, L);
+  __syncthreads();
+}
+
+template <typename Real, class PL, int DT>
+__global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))) k_pass1(PassArgs a) {
+  __shared__ cplx<Real> lds[PassLds<Real, PL>::X1];
+  __shared__ cplx<Real> tw[PL::N1];
+  init_twiddles<Real, PL::N1, PL::T1>(tw);
+  pass1_body<Real, PL, DT>(a, lds, tw, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,34 +208,40 @@ __device__ __forceinline__ void pass2_fetch_item(cplx<Real> (&v)[2][PL::E2], con
   pass2_fetch<Real, PL>(v, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, item - slot * PL::TILES2, r, p);
 }
 
+// Pass 2 on the items of `a` taken by work-group `block` of `nblocks` (tw holds
+// the length-N2 twiddles).
 template <typename Real, class PL>
-__global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
-  constexpr int LP = lds_padded_len(PL::N2);
-  __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::RW * LP];
-  __shared__ cplx<Real> tw[PL::N2];
+__device__ __forceinline__ void pass2_body(PassArgs a, cplx<Real>* lds, const cplx<Real>* tw, int block,
+                                           int nblocks) {
+  constexpr int LP = PassLds<Real, PL>::LP2;
   const int tid = threadIdx.x;
-  for (int m = tid; m < PL::N2; m += PL::T2) tw[m] = twiddle<Real>(m, PL::N2);
-  __syncthreads();
-  const int items = launch_span<Real, PL>(a) * PL::TILES2;
+  const int items = launch_span(a) * PL::TILES2;
   const int p = tid % PL::P2, r = tid / PL::P2;
   cplx<Real>* buf0 = lds + r * LP;
   cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::RW + r) * LP : buf0;
   const int lane = tid & 63, wave = tid >> 6;
-  const int G = gridDim.x;
   // software pipeline over two register sets: the rows of the next item are
   // fetched while this one is transformed
   cplx<Real> va[2][PL::E2], vb[2][PL::E2];
-  int item = blockIdx.x;
+  int item = block;
   if (item < items) pass2_fetch_item<Real, PL>(va, a, item, r, p);
   while (item < items) {
-    const int next = item + G;
+    const int next = item + nblocks;
     if (next < items) pass2_fetch_item<Real, PL>(vb, a, next, r, p);
     pass2_item<Real, PL>(va, a, item, buf0, buf1, tw, r, p, lane, wave);
     if (next >= items) break;
-    item = next + G;
+    item = next + nblocks;
     if (item < items) pass2_fetch_item<Real, PL>(va, a, item, r, p);
     pass2_item<Real, PL>(vb, a, next, buf0, buf1, tw, r, p, lane, wave);
   }
+}
+
+template <typename Real, class PL>
+__global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
+  __shared__ cplx<Real> lds[PassLds<Real, PL>::X2];
+  __shared__ cplx<Real> tw[PL::N2];
+  init_twiddles<Real, PL::N2, PL::T2>(tw);
+  pass2_body<Real, PL>(a, lds, tw, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -77,8 +77,6 @@ struct fcas_ctx {
   int n_cu = 0;                     // compute units of the device
   int fused_cap[kNumPlans] = {0};   // resident work-groups of each fused kernel (0 = not queried)
   int32_t* d_done = nullptr;        // [kNumPlans][2][max_batch] fused-schedule tile counters
-  hipStream_t aux = nullptr;        // second stream of the two-stream schedule
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool timing = false;
   std::vector<TimedPair> t_pass1, t_pass2, t_fused;
   int grid1[kNumPlans], grid2[kNumPlans];   // persistent grid sizes of the two passes
@@ -127,9 +125,8 @@ int validate_config(const fcas_config* c) {
   if (plan_for_length(c->max_samples) < 0)
     return fail(FCAS_EUNSUPPORTED_N, "max_samples %lld has no FFT plan", (long long)c->max_samples);
   if (c->workspace_bytes < 0) return fail(FCAS_EINVAL, "workspace_bytes must be >= 0");
-  if (c->schedule != FCAS_SCHEDULE_FUSED && c->schedule != FCAS_SCHEDULE_TWO_PASS &&
-      c->schedule != FCAS_SCHEDULE_TWO_STREAMS)
-    return fail(FCAS_EINVAL, "schedule must be FCAS_SCHEDULE_FUSED, _TWO_PASS or _TWO_STREAMS");
+  if (c->schedule != FCAS_SCHEDULE_FUSED && c->schedule != FCAS_SCHEDULE_TWO_PASS)
+    return fail(FCAS_EINVAL, "schedule must be FCAS_SCHEDULE_FUSED or FCAS_SCHEDULE_TWO_PASS");
   for (int d = 0; d < 4; ++d) {
     if (!std::isfinite(c->box_lo[d]) || !std::isfinite(c->box_hi[d]) || !(c->box_hi[d] >= c->box_lo[d]))
       return fail(FCAS_EINVAL, "search box coordinate %d must satisfy lo <= hi (finite)", d);
@@ -160,9 +157,6 @@ int free_all(fcas_ctx* c) {
   for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_pass2) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_fused) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
-  if (c->ev_fork) hipEventDestroy(c->ev_fork);
-  if (c->ev_join) hipEventDestroy(c->ev_join);
-  if (c->aux) hipStreamDestroy(c->aux);
   return FCAS_OK;
 }
 
@@ -240,8 +234,7 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
     c->grid1[i] = c->grid2[i] = kDefaultGrid;
     c->chosen[i] = i;
   }
-  c->schedule = cfg->schedule == FCAS_SCHEDULE_FUSED ? (c->prec == 0 ? FCAS_SCHEDULE_FUSED : FCAS_SCHEDULE_TWO_PASS)
-                                                      : cfg->schedule;
+  c->schedule = c->prec == 0 ? cfg->schedule : FCAS_SCHEDULE_TWO_PASS;
   if (hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || c->n_cu < 1)
     c->n_cu = 1;
   c->elt = c->prec ? 16 : 8;
@@ -286,15 +279,6 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
     free_all(c);
     delete c;
     g_last_error = msg;
-    return rc;
-  }
-  if (c->schedule == FCAS_SCHEDULE_TWO_STREAMS &&
-      ((e = hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking)) != hipSuccess ||
-       (e = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess ||
-       (e = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess)) {
-    rc = hip_fail(e, "second stream of the two-stream schedule");
-    free_all(c);
-    delete c;
     return rc;
   }
   int32_t parts2[kNumPlans];
@@ -473,8 +457,6 @@ PassArgs pass_args(fcas_ctx* ctx, int plan, int cap) {
   a.n_det = ctx->net.n_det;
   a.chunk_begin = 0;
   a.cap = cap;
-  a.split_part = 0;
-  a.split_parts = 1;
   return a;
 }
 
@@ -526,22 +508,8 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
   if (ctx->schedule == FCAS_SCHEDULE_FUSED &&
       (e = launch_zero_i32(ctx->d_done, 2 * kNumPlans * ctx->cfg.max_batch, s)) != hipSuccess)
     return hip_fail(e, "zero tile counters");
-  // Two-stream schedule: fork after the set-up; between plans (which reuse the
-  // workspace from its start) both streams wait for each other; join before
-  // finalize.
-  const bool split = ctx->schedule == FCAS_SCHEDULE_TWO_STREAMS && n >= 2;
-  auto fork = [&]() {
-    return (e = hipEventRecord(ctx->ev_fork, s)) == hipSuccess && (e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0)) == hipSuccess;
-  };
-  auto join = [&]() {
-    return (e = hipEventRecord(ctx->ev_join, ctx->aux)) == hipSuccess && (e = hipStreamWaitEvent(s, ctx->ev_join, 0)) == hipSuccess;
-  };
-  if (split && !fork()) return hip_fail(e, "fork of the second stream");
-  bool first_plan = true;
   for (int plan = 0; plan < kNumPlans; ++plan) {
     if (ctx->plan_refs[plan] <= 0) continue;
-    if (split && !first_plan && !(join() && fork())) return hip_fail(e, "synchronisation of the two streams");
-    first_plan = false;
     const PlanInfo& pi = kPlans[plan];
     const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
     int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
@@ -551,39 +519,15 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
       continue;
     }
     PassArgs a = pass_args(ctx, plan, cap);
-    if (split && n <= cap) {
-      // one chunk, split in two shares: share 0 on the caller's stream, share 1 on the second stream
-      a.split_parts = 2;
-      const int m = (n + 1) / 2;
-      const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
-      const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
-      for (int part = 0; part < 2; ++part) {
-        hipStream_t sp = part == 0 ? s : ctx->aux;
-        a.split_part = part;
-        if ((e = timed_launch(ctx, ctx->t_pass1, sp, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
-        if ((e = timed_launch(ctx, ctx->t_pass2, sp, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
-      }
-      continue;
-    }
-    // Chunks of the workspace size; with two streams (and room for two
-    // evaluations), chunks of half of it alternate between the streams, each
-    // stream on its own half.
-    const bool alternate = split && cap >= 2;
-    const int step = alternate ? cap / 2 : cap;
-    a.cap = step;
-    for (int begin = 0, k = 0; begin < n; begin += step, ++k) {
-      const bool second = alternate && (k & 1);
+    for (int begin = 0; begin < n; begin += cap) {
       a.chunk_begin = begin;
-      a.ws = (char*)ctx->d_ws + (second ? (size_t)step * slot_bytes : 0);
-      const int m = std::min(step, n - begin);
+      const int m = std::min(cap, n - begin);
       const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
       const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
-      hipStream_t sp = second ? ctx->aux : s;
-      if ((e = timed_launch(ctx, ctx->t_pass1, sp, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
-      if ((e = timed_launch(ctx, ctx->t_pass2, sp, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
+      if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
+      if ((e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
     }
   }
-  if (split && !join()) return hip_fail(e, "join of the second stream");
   if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->d_plan_parts2,
                            ctx->d_counts, ctx->d_evaluated, d_fitness, d_argmax, s)) != hipSuccess)
     return hip_fail(e, "finalize launch");

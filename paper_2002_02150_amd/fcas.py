@@ -21,7 +21,6 @@ MIXED = 0
 FP64 = 1
 SCHEDULE_FUSED = 0
 SCHEDULE_TWO_PASS = 1
-SCHEDULE_TWO_STREAMS = 2
 MAX_DET = 8
 
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP", -5: "ENOMEM", -6: "ECAPACITY"}

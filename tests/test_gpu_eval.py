@@ -244,76 +244,3 @@ def oracle_eval_range(case, thetas, j_range):
     import synth
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
     return F.fitness_batch(case.seg, case.net.pos_m, case.net.tensor, thetas, np.array(lo), np.array(hi), j_range)
-
-
-@pytest.mark.parametrize("ws_slots", [0, 3], ids=["one-chunk", "chunked"])
-def test_two_stream_schedule_is_bitwise_two_pass(ws_slots):
-    """The two-stream schedule splits the points of each plan in two shares
-    that run on two streams; every point goes through the same kernels, so the
-    results equal the two-pass schedule's bit for bit: on a ragged batch over
-    three segment lengths (three plans sharing the workspace), an odd batch,
-    one point, a batch with most points outside the rectangle, and a
-    workspace small enough to force chunking (no split then)."""
-    require_gpu()
-    cases = [Case("HLVK", n, 2048.0, snr=12.0, cfg=18, realization=i) for i, n in enumerate((16384, 24576, 8192))]
-    rng = np.random.default_rng(23)
-    ths, segs = [], []
-    for i, c in enumerate(cases):
-        t = thetas_for(c, rng, n_near=25, n_uniform=26)
-        ths.append(t)
-        segs.append(np.full(len(t), i, dtype=np.int32))
-    order = rng.permutation(sum(len(t) for t in ths))
-    th = torch.from_numpy(np.concatenate(ths)[order]).to(dev())
-    sg = torch.from_numpy(np.concatenate(segs)[order]).to(dev())
-    wsb = ws_slots * 2 * 24576 * 8
-    two = make_ctx(cases[0], 0, max_batch=th.shape[0], max_segments=3, max_samples=24576, schedule=1)
-    split = make_ctx(cases[0], 0, max_batch=th.shape[0], max_segments=3, max_samples=24576, workspace_bytes=wsb,
-                     schedule=2)
-    for i, c in enumerate(cases):
-        upload(two, i, c)
-        upload(split, i, c)
-    outside = th.clone()
-    outside[: th.shape[0] * 3 // 4, 2] = 1e3          # tau0 far outside the rectangle
-    for t, s in [(th, sg), (th[:-1], sg[:-1]), (th[:1], sg[:1]), (outside, sg)]:
-        f1, j1 = two.eval(t, s)
-        f2, j2 = split.eval(t, s)
-        assert torch.equal(f1, f2) and torch.equal(j1, j2)
-    assert split.device_error() == 0
-    two.close()
-    split.close()
-
-
-def test_two_stream_schedule_in_a_graph():
-    """A fitness call of the two-stream schedule captured into a HIP graph
-    (fork and join through events) replays to the eager results, replay after
-    replay, with other eager work and synchronisations in between."""
-    require_gpu()
-    case = Case("HLVK", 16384, 2048.0, snr=12.0, cfg=19)
-    rng = np.random.default_rng(29)
-    th_all = [torch.from_numpy(thetas_for(case, rng, n_near=40, n_uniform=40, extras=False)).to(dev())
-              for _ in range(3)]
-    n = th_all[0].shape[0]
-    ctx = make_ctx(case, 0, max_batch=n, schedule=2)
-    upload(ctx, 0, case)
-    seg = torch.zeros(n, dtype=torch.int32, device=dev())
-    th = th_all[0].clone()
-    f = torch.empty(n, dtype=torch.float64, device=dev())
-    j = torch.empty(n, dtype=torch.int32, device=dev())
-    expect = [ctx.eval(t, seg) for t in th_all]
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(s):
-        ctx.eval(th, seg, f, j)
-    torch.cuda.current_stream().wait_stream(s)
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(g):
-        ctx.eval(th, seg, f, j)
-    for rep in range(6):
-        k = rep % 3
-        th.copy_(th_all[k])
-        g.replay()
-        torch.cuda.synchronize()
-        assert torch.equal(f, expect[k][0]) and torch.equal(j, expect[k][1]), f"replay {rep}"
-        ctx.eval(th_all[(k + 1) % 3], seg)   # eager work between replays
-        torch.cuda.synchronize()
-    ctx.close()
