@@ -29,6 +29,10 @@ def common_flags():
     return ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             # no packed FP32 instructions anywhere in the device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            # multiply-adds are fused only within one source expression, so every
+            # inlined copy of a tile function rounds the same way (bitwise-repeatable
+            # results whatever work-group or schedule evaluates a point)
+            "-ffp-contract=on",
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-value", "-Wno-unused-result"]
 
 

@@ -167,9 +167,9 @@ __global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))
 
 // ---------------------------------------------------------------------------
 // Pass 2: length-N2 row FFTs, |a_0|^2 + |a_1|^2 and its maximum over the rows
-// of one work item -> one partial (value, sample) per wavefront.  Every row
-// transform lies inside one wavefront, so the items need no work-group
-// barrier.
+// of one work item -> one partial (value, sample) per wavefront.  When every
+// row transform lies inside one wavefront the items need no work-group
+// barrier; rows longer than a wavefront's share synchronise the work-group.
 // ---------------------------------------------------------------------------
 template <typename Real, class PL>
 __device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const PassArgs& a, int item,
@@ -179,8 +179,11 @@ __device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const Pas
   const int slot = item / PL::TILES2;
   const int tile = item - slot * PL::TILES2;
   const int e = a.list[a.chunk_begin + slot];
+  // row transforms held by one wavefront exchange through LDS without a
+  // work-group barrier
+  constexpr bool WAVE = (64 % PL::P2) == 0;
   pass2_twiddle<Real, PL>(v, tile, r, p);
-  run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, true>(v, buf0, buf1, tw, p);
+  run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf0, buf1, tw, p);
   const SegDesc& sg = a.segs[a.evals[e].seg];
   Real g;
   int j;

@@ -141,12 +141,29 @@ template <typename T>
 FCAS_HD void dft3(cplx<T>& x0, cplx<T>& x1, cplx<T>& x2) {
   // w = e^{+2 pi i/3} = -1/2 + i sqrt(3)/2
   const T h = (T)0.86602540378443864676;
-  cplx<T> s = add(x1, x2), d = sub(x1, x2);
-  cplx<T> m = sub(x0, scale(s, (T)0.5));
-  cplx<T> r = scale(mul_i(d), h);
+  const cplx<T> s = add(x1, x2), d = sub(x1, x2);
+  const cplx<T> m = mk<T>(x0.x - (T)0.5 * s.x, x0.y - (T)0.5 * s.y);
+  // i h d = (-h d.y, h d.x)
   x0 = add(x0, s);
-  x1 = add(m, r);
-  x2 = sub(m, r);
+  x1 = mk<T>(m.x - h * d.y, m.y + h * d.x);
+  x2 = mk<T>(m.x + h * d.y, m.y - h * d.x);
+}
+
+// Last step of an 8-point DFT from the 4-point DFTs of the even (e) and odd
+// (o) inputs: X[j] = e_j + w8^j o_j, X[j+4] = e_j - w8^j o_j.  The 1/sqrt2 of
+// w8^1 = (1+i)/sqrt2 and w8^3 = (-1+i)/sqrt2 is applied inside the sums, each
+// output component one expression (a single fused multiply-add).
+template <typename T>
+FCAS_HD void dft8_combine(cplx<T>* x, cplx<T> e0, cplx<T> e1, cplx<T> e2, cplx<T> e3, cplx<T> o0, cplx<T> o1,
+                          cplx<T> o2, cplx<T> o3) {
+  const T r = (T)0.70710678118654752440;
+  const T a1 = o1.x - o1.y, b1 = o1.x + o1.y;    // (1+i) o1
+  const T a3 = -o3.x - o3.y, b3 = o3.x - o3.y;   // (-1+i) o3
+  const cplx<T> t2 = mul_i(o2);                  // w8^2 = i
+  x[0] = add(e0, o0); x[4] = sub(e0, o0);
+  x[1] = mk<T>(e1.x + r * a1, e1.y + r * b1); x[5] = mk<T>(e1.x - r * a1, e1.y - r * b1);
+  x[2] = add(e2, t2); x[6] = sub(e2, t2);
+  x[3] = mk<T>(e3.x + r * a3, e3.y + r * b3); x[7] = mk<T>(e3.x - r * a3, e3.y - r * b3);
 }
 
 template <typename T>
@@ -156,14 +173,7 @@ FCAS_HD void dft8(cplx<T>* x) {
   cplx<T> o0 = x[1], o1 = x[3], o2 = x[5], o3 = x[7];
   dft4(e0, e1, e2, e3);
   dft4(o0, o1, o2, o3);
-  const T r = (T)0.70710678118654752440;
-  cplx<T> t1 = scale(mk<T>(o1.x - o1.y, o1.x + o1.y), r);   // w8^1 = (1+i)/sqrt2
-  cplx<T> t2 = mul_i(o2);                                      // w8^2 = i
-  cplx<T> t3 = scale(mk<T>(-o3.x - o3.y, o3.x - o3.y), r);  // w8^3 = (-1+i)/sqrt2
-  x[0] = add(e0, o0); x[4] = sub(e0, o0);
-  x[1] = add(e1, t1); x[5] = sub(e1, t1);
-  x[2] = add(e2, t2); x[6] = sub(e2, t2);
-  x[3] = add(e3, t3); x[7] = sub(e3, t3);
+  dft8_combine(x, e0, e1, e2, e3, o0, o1, o2, o3);
 }
 
 template <typename T>
@@ -215,14 +225,7 @@ FCAS_HD void dft_half(cplx<T>* x) {
     cplx<T> e0 = x[0], e1 = x[2], e2, e3, o0 = x[1], o1 = x[3], o2, o3;
     dft4_half(e0, e1, e2, e3);
     dft4_half(o0, o1, o2, o3);
-    const T r = (T)0.70710678118654752440;
-    cplx<T> t1 = scale(mk<T>(o1.x - o1.y, o1.x + o1.y), r);
-    cplx<T> t2 = mul_i(o2);
-    cplx<T> t3 = scale(mk<T>(-o3.x - o3.y, o3.x - o3.y), r);
-    x[0] = add(e0, o0); x[4] = sub(e0, o0);
-    x[1] = add(e1, t1); x[5] = sub(e1, t1);
-    x[2] = add(e2, t2); x[6] = sub(e2, t2);
-    x[3] = add(e3, t3); x[7] = sub(e3, t3);
+    dft8_combine(x, e0, e1, e2, e3, o0, o1, o2, o3);
   } else if constexpr (R == 16) {
     cplx<T> y[16];
 #pragma unroll

@@ -257,7 +257,7 @@ struct Plan {
   static_assert(Rad2::product() == N2, "pass-2 radices must multiply to N2");
   static_assert(N1 % E1 == 0 && N2 % E2 == 0, "elements per thread must divide the length");
   static_assert(N2 % C == 0 && N1 % RW == 0, "tiles must divide the transform");
-  static_assert(T2 % 64 == 0 && 64 % P2 == 0, "pass-2 rows lie inside whole wavefronts");
+  static_assert(T2 % 64 == 0 && (64 % P2 == 0 || P2 % 64 == 0), "pass-2 rows and wavefronts must nest");
 };
 
 // ---------------------------------------------------------------------------

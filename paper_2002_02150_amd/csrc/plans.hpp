@@ -11,7 +11,7 @@
 namespace fcas {
 
 // Pass 2 leaves one partial (maximum, sample) per wavefront of each work item:
-// TILES2 * T2 / 64 per evaluation, at most N1 * P2 / 64 = 512 over all plans.
+// TILES2 * T2 / 64 per evaluation, at most 512 over all plans.
 constexpr int kMaxParts2 = 512;
 
 template <int... R>
@@ -40,7 +40,8 @@ using Rad = Radices<R...>;
   X(16, 262144,   256, 16, (16, 16),    16, 8,  1024, 16, (16, 16, 4),    4, 2)                    \
   X(17,  65536,   128, 16, (16, 8),     32, 16,  512, 8, (8, 8, 8),       4, 4)                    \
   X(18, 196608,   256, 16, (16, 16),    16, 8,   768, 12, (4, 4, 4, 4, 3), 4, 4)                   \
-  X(19,   8192,   128, 16, (16, 8),     32, 16,   64, 8, (8, 8),          32, 16)
+  X(19,   8192,   128, 16, (16, 8),     32, 16,   64, 8, (8, 8),          32, 16)                  \
+  X(20, 262144,   256, 8, (8, 8, 4),    8, 8,   1024, 8, (8, 8, 8, 2),    2, 2)
 // clang-format on
 
 #define FCAS_UNPAREN(...) __VA_ARGS__
@@ -53,7 +54,7 @@ using Rad = Radices<R...>;
 
 FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
 
-constexpr int kNumPlans = 20;
+constexpr int kNumPlans = 21;
 
 struct PlanInfo {
   int64_t n;

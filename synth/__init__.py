@@ -173,3 +173,22 @@ def near_point(rng: np.random.Generator, n: int, centre, lo, hi, frac=0.01):
 # Rounded outwards to 6 significant digits.
 SEARCH_BOX_30HZ_LO = (0.0, -math.pi / 2, 15.0336, 0.841913)
 SEARCH_BOX_30HZ_HI = (2.0 * math.pi, math.pi / 2, 93.8141, 1.75126)
+
+
+def td_noise(rng: np.random.Generator, n_samples: int, fs: float, f_min: float = 20.0, s0: float = 1.0):
+    """Real Gaussian time series of n_samples at fs whose one-sided PSD is the
+    analytic curve above f_min and zero below it (no power far below the band,
+    so cutting segments out of the series leaks none into it).
+
+    Drawn in the frequency domain in continuum units, n_k = sqrt(T S_k / 4)
+    (g + i g'), then x = fs * irfft(n) (continuum units are dt times the DFT)."""
+    f = np.arange(n_samples // 2 + 1) * (fs / n_samples)
+    psd = psd_analytic(f, s0)
+    psd[f < f_min] = np.inf            # fd_noise leaves those bins at zero
+    return fs * np.fft.irfft(fd_noise(rng, psd, n_samples, fs), n=n_samples)
+
+
+def segment_fd(x, start: int, n_samples: int, fs: float):
+    """One-sided Fourier data (continuum units, dt times the DFT) of the
+    rectangular window x[start : start + n_samples]."""
+    return np.fft.rfft(x[start:start + n_samples]) / fs

@@ -148,3 +148,21 @@ def test_pso_search_recovers_injection():
     bf, bt, bj, br = graph.best()
     assert bf.item() >= 0.95 * f0.item(), (bf.item(), f0.item())
     ctx.close()
+
+
+def test_full_search_small():
+    """The full-length search (segments cut from one time series, per-segment
+    coalescence ranges that tile the data, one batched swarm over all
+    segments, polish of each segment's best) runs end to end at a small size;
+    the polish never lowers a segment's best fitness, and every reported
+    injection lies in the searched range of its segment."""
+    require_gpu()
+    from paper_2002_02150_amd.full_search import layout, run
+    out = run(minutes=4.0, n_seg=3, iters=30, n_inj=1, polish_steps=3, log=lambda s: None)
+    assert out["segments"] == 3 and out["iterations"] == 30
+    assert out["t_run_s"] > 0 and out["evaluated_points"] > 0
+    starts, stride, ranges = layout(int(4 * 60 * 2048), 3)
+    assert stride == out["stride_samples"]
+    for d in out["injections"]:
+        assert d["rho_sq"] >= d["rho_sq_pso"] - 1e-9
+        assert d["rho0_sq"] > 0
