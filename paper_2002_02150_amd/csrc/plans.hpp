@@ -41,7 +41,11 @@ using Rad = Radices<R...>;
   X(17,  65536,   128, 16, (16, 8),     32, 16,  512, 8, (8, 8, 8),       4, 4)                    \
   X(18, 196608,   256, 16, (16, 16),    16, 8,   768, 12, (4, 4, 4, 4, 3), 4, 4)                   \
   X(19,   8192,   128, 16, (16, 8),     32, 16,   64, 8, (8, 8),          32, 16)                  \
-  X(20, 262144,   256, 8, (8, 8, 4),    8, 8,   1024, 8, (8, 8, 8, 2),    2, 2)
+  X(20, 262144,   256, 8, (8, 8, 4),    8, 8,   1024, 8, (8, 8, 8, 2),    2, 2)                    \
+  X(21, 196608,   256, 8, (8, 8, 4),    8, 8,    768, 12, (4, 4, 4, 4, 3), 4, 4)                   \
+  X(22,  65536,   256, 8, (8, 8, 4),    8, 8,    256, 8, (8, 8, 4),       8, 8)                    \
+  X(23,  65536,   128, 8, (8, 4, 4),    16, 16,  512, 8, (8, 8, 8),       4, 4)                    \
+  X(24, 131072,   128, 8, (8, 4, 4),    16, 16, 1024, 8, (8, 8, 8, 2),    2, 2)
 // clang-format on
 
 #define FCAS_UNPAREN(...) __VA_ARGS__
@@ -54,7 +58,7 @@ using Rad = Radices<R...>;
 
 FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
 
-constexpr int kNumPlans = 21;
+constexpr int kNumPlans = 25;
 
 struct PlanInfo {
   int64_t n;
