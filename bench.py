@@ -2,10 +2,10 @@
 
 One step is one iteration of the PSO search of the 4-detector, 64 s, 2048 Hz
 configuration (131072 samples per detector, SNR-10 injection): the fitness of
-8 runs x 40 particles (320 evaluations), the swarm update and the best of the
-runs, captured as HIP graphs of 20 iterations and replayed; by default the
-timed region is one whole search (2000 iterations) and ends with the gradient
-polish of the best point.  value = fitness evaluations of the
+8 runs x 40 particles (320 evaluations) and the swarm update, captured as HIP
+graphs of 20 iterations and replayed; by default the timed region is one whole
+search (2000 iterations) and ends with the best of the runs and the gradient
+polish of that point.  value = fitness evaluations of the
 particles per second over the timed region (inputs resident in HBM).  A second
 timed region launches the same steps eagerly with HIP events around the FFT
 pass kernels, for the roofline figures.
@@ -84,8 +84,8 @@ def make_workload(torch, dev, schedule):
 
 class Search:
     """The search of the benchmark configuration on preallocated buffers: one
-    iteration is the fitness of all particles, the swarm update and the best
-    of the runs; after the iterations the best point is polished."""
+    iteration is the fitness of all particles and the swarm update; after the
+    iterations the best of the runs is taken and that point polished."""
 
     def __init__(self, torch, ctx, sw):
         self.torch, self.ctx, self.sw = torch, ctx, sw
@@ -105,7 +105,6 @@ class Search:
         self.ctx.eval(self.sw.theta, self.seg, self.f, self.j)
         self.ctx.set_timing(False)
         self.sw.step(self.f, self.j)
-        self.sw.best()
 
     def capture(self, group):
         """Captures two HIP graphs: `group` iterations, and one iteration."""
@@ -132,7 +131,9 @@ class Search:
             self.graph1.replay()
 
     def polish(self):
+        """Best of the runs (Sec. III), then the gradient polish of that point."""
         from paper_2002_02150_amd import polish
+        self.sw.best()
         self.pol_theta.copy_(self.sw.out_theta.view(1, 4))
         polish(self.ctx, self.pol_theta, self.seg1, steps=POLISH_STEPS, step_frac=1e-3, trials=8,
                fitness=self.pol_f, argmax=self.pol_j)
@@ -343,7 +344,7 @@ def main():
         search.iteration()
     search.capture(GRAPH_GROUP)   # one more iteration, then graphs of GRAPH_GROUP and 1 iterations
     torch.cuda.synchronize()
-    # timed region 1: K iterations (graph replays) and the polish of the best point
+    # timed region 1: K iterations (graph replays), the best of the runs and its polish
     ev0 = ctx.evaluated()
     t = time.perf_counter()
     search.run(a.steps)
@@ -411,8 +412,8 @@ def main():
         "dtype": "f32+f64phase", "data": "synthetic",
         "config": {"workload": "4 detectors (HLVK), 64 s at 2048 Hz (131072 samples), SNR-10 SPA injection; "
                                "PSO 8 runs x 40 particles, one step = fitness of the 320 particles + swarm update "
-                               "+ best of runs (a captured HIP graph); the timed region ends with a "
-                               f"{POLISH_STEPS}-step gradient polish of the best point",
+                               "(captured HIP graphs of 20 steps); the timed region ends with the best of the runs "
+                               f"and a {POLISH_STEPS}-step gradient polish of that point",
                    "global_batch": RUNS * PARTICLES, "seq_len": N_SAMPLES, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,

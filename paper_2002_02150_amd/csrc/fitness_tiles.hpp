@@ -71,87 +71,121 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kC = 299792458.0;
 
 // ---------------------------------------------------------------------------
-// Set-up, one thread per parameter point, FP64 (chirp times, delays, antenna
-// patterns, orthonormal basis).  Sec. II.B (chirp times), Sec. II (eq.
-// detresponse: delays, antenna pattern matrix), Sec. II.C (U = F(psi = 0)).
+// Set-up of one parameter point, FP64 (chirp times, delays, antenna patterns,
+// orthonormal basis).  Sec. II.B (chirp times), Sec. II (eq. detresponse:
+// delays, antenna pattern matrix), Sec. II.C (U = F(psi = 0)).
+//
+// Written once for two executions: `Dets` is either a loop over the
+// detectors (setup_one, one thread per point) or a group of lanes with one
+// detector each, whose sums over detectors are lane reductions (the kernel).
+// Per-detector values live in the point's descriptor; a lane only ever reads
+// back the entries it wrote itself.
 // ---------------------------------------------------------------------------
-FCAS_HD void setup_one(const NetDesc& net, const SegDesc& sg, const double* th, EvalDesc& ev) {
+struct SkyFrame {
+  double n[3], ex[3], ey[3];   // propagation direction and wave axes (-alpha_hat, delta_hat)
+};
+
+// Phase coefficients (cycles) and the sky frame of a point.
+FCAS_HD void setup_point(const NetDesc& net, const double* th, double coef[4], SkyFrame& fr) {
   const double alpha = th[0], delta = th[1], tau0 = th[2], tau15 = th[3];
   const double fs = net.f_star;
-  // chirp times -> phase coefficients (cycles)
   const double v0 = cbrt(5.0 * tau15 / (32.0 * kPi * tau0));
   const double eta = 1.0 / (8.0 * fs * tau15 * v0 * v0);
   const double tau1 = 5.0 / (192.0 * kPi * fs * eta * v0 * v0 * v0) * (743.0 / 336.0 + 11.0 * eta / 4.0);
   const double tau2 = 5.0 / (128.0 * kPi * fs * eta * v0) *
                       (3058673.0 / 1016064.0 + 5429.0 * eta / 1008.0 + 617.0 * eta * eta / 144.0);
-  ev.coef[0] = fs * 0.6 * tau0;
-  ev.coef[1] = fs * tau1;
-  ev.coef[2] = -fs * 1.5 * tau15;
-  ev.coef[3] = fs * 3.0 * tau2;
-  // sky direction and wave axes (-alpha_hat, delta_hat)
+  coef[0] = fs * 0.6 * tau0;
+  coef[1] = fs * tau1;
+  coef[2] = -fs * 1.5 * tau15;
+  coef[3] = fs * 3.0 * tau2;
   double sa, ca, sd, cd;
   sincos(alpha, &sa, &ca);
   sincos(delta, &sd, &cd);
-  const double n[3] = {cd * ca, cd * sa, sd};
-  const double ex[3] = {sa, -ca, 0.0};
-  const double ey[3] = {-sd * ca, -sd * sa, cd};
-  double vf = 0.0;
-  for (int i = 0; i < net.n_det; ++i) {
-    const double* r = net.pos[i];
-    ev.dly[i] = -(n[0] * r[0] + n[1] * r[1] + n[2] * r[2]) / kC * sg.df;
-    {
-      const double ps = (double)sg.dk1 * ev.dly[i];
-      double ss, cs;
-      sincos_rev(ps - rint(ps), &ss, &cs);
-      ev.step1[i][0] = cs;
-      ev.step1[i][1] = ss;
-      ev.step1f[i][0] = (float)cs;
-      ev.step1f[i][1] = (float)ss;
+  fr.n[0] = cd * ca; fr.n[1] = cd * sa; fr.n[2] = sd;
+  fr.ex[0] = sa; fr.ex[1] = -ca; fr.ex[2] = 0.0;
+  fr.ey[0] = -sd * ca; fr.ey[1] = -sd * sa; fr.ey[2] = cd;
+}
+
+// Detector i: delay ramp (cycles per bin), its pass-1 step, and row i of V.
+FCAS_HD void setup_detector(const NetDesc& net, const SegDesc& sg, const SkyFrame& fr, int i, EvalDesc& ev) {
+  const double* r = net.pos[i];
+  ev.dly[i] = -(fr.n[0] * r[0] + fr.n[1] * r[1] + fr.n[2] * r[2]) / kC * sg.df;
+  const double ps = (double)sg.dk1 * ev.dly[i];
+  double ss, cs;
+  sincos_rev(ps - rint(ps), &ss, &cs);
+  ev.step1[i][0] = cs;
+  ev.step1[i][1] = ss;
+  ev.step1f[i][0] = (float)cs;
+  ev.step1f[i][1] = (float)ss;
+  double up = 0.0, uc = 0.0;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      const double d = net.ten[i][a][b];
+      up += d * (fr.ex[a] * fr.ex[b] - fr.ey[a] * fr.ey[b]);
+      uc += d * (fr.ex[a] * fr.ey[b] + fr.ey[a] * fr.ex[b]);
     }
-    double up = 0.0, uc = 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) {
-        const double d = net.ten[i][a][b];
-        up += d * (ex[a] * ex[b] - ey[a] * ey[b]);
-        uc += d * (ex[a] * ey[b] + ey[a] * ex[b]);
-      }
-    ev.v[i][0] = sg.sigma[i] * up;
-    ev.v[i][1] = sg.sigma[i] * uc;
-    vf += ev.v[i][0] * ev.v[i][0] + ev.v[i][1] * ev.v[i][1];
-  }
-  // modified Gram-Schmidt (twice) on the columns of V, larger column first
-  double n0 = 0.0, n1 = 0.0;
-  for (int i = 0; i < net.n_det; ++i) {
-    n0 += ev.v[i][0] * ev.v[i][0];
-    n1 += ev.v[i][1] * ev.v[i][1];
-  }
-  const int ca_ = (n1 > n0) ? 1 : 0, cb_ = 1 - ca_;
-  const double na = sqrt(ca_ ? n1 : n0);
+  ev.v[i][0] = sg.sigma[i] * up;
+  ev.v[i][1] = sg.sigma[i] * uc;
+}
+
+// Orthonormal basis Q of span(V): modified Gram-Schmidt, twice, larger
+// column first; q[i][1] holds the residual of the second column until it is
+// normalised.  Returns the rank (0, 1 or 2).
+template <class Dets>
+FCAS_HD int setup_basis(EvalDesc& ev, const Dets& dets) {
+  const double n0 = dets.sum([&](int i) { return ev.v[i][0] * ev.v[i][0]; });
+  const double n1 = dets.sum([&](int i) { return ev.v[i][1] * ev.v[i][1]; });
+  const double vf = n0 + n1;
+  const int ca = (n1 > n0) ? 1 : 0, cb = 1 - ca;
+  const double na = sqrt(ca ? n1 : n0);
+  dets.all([&](int i) { ev.q[i][0] = ev.q[i][1] = 0.0; });
   int rank = 0;
-  for (int i = 0; i < kMaxDet; ++i) ev.q[i][0] = ev.q[i][1] = 0.0;
   if (na > 0.0) {
     rank = 1;
-    for (int i = 0; i < net.n_det; ++i) ev.q[i][0] = ev.v[i][ca_] / na;
-    double bres[kMaxDet];
-    for (int i = 0; i < net.n_det; ++i) bres[i] = ev.v[i][cb_];
+    dets.each([&](int i) {
+      ev.q[i][0] = ev.v[i][ca] / na;
+      ev.q[i][1] = ev.v[i][cb];
+    });
     for (int pass = 0; pass < 2; ++pass) {
-      double dot = 0.0;
-      for (int i = 0; i < net.n_det; ++i) dot += ev.q[i][0] * bres[i];
-      for (int i = 0; i < net.n_det; ++i) bres[i] -= dot * ev.q[i][0];
+      const double dot = dets.sum([&](int i) { return ev.q[i][0] * ev.q[i][1]; });
+      dets.each([&](int i) { ev.q[i][1] -= dot * ev.q[i][0]; });
     }
-    double nb = 0.0;
-    for (int i = 0; i < net.n_det; ++i) nb += bres[i] * bres[i];
-    nb = sqrt(nb);
+    const double nb = sqrt(dets.sum([&](int i) { return ev.q[i][1] * ev.q[i][1]; }));
     if (nb > 1e-10 * sqrt(vf)) {
       rank = 2;
-      for (int i = 0; i < net.n_det; ++i) ev.q[i][1] = bres[i] / nb;
+      dets.each([&](int i) { ev.q[i][1] /= nb; });
+    } else {
+      dets.each([&](int i) { ev.q[i][1] = 0.0; });
     }
   }
-  ev.rank = rank;
-  for (int i = 0; i < kMaxDet; ++i) {
+  dets.all([&](int i) {
     ev.qf[i][0] = (float)ev.q[i][0];
     ev.qf[i][1] = (float)ev.q[i][1];
+  });
+  return rank;
+}
+
+// The detectors as a loop of one thread.
+struct DetLoop {
+  int n_det;
+  template <class F> FCAS_HD double sum(F f) const {
+    double acc = 0.0;
+    for (int i = 0; i < n_det; ++i) acc += f(i);
+    return acc;
   }
+  template <class F> FCAS_HD void each(F f) const {
+    for (int i = 0; i < n_det; ++i) f(i);
+  }
+  template <class F> FCAS_HD void all(F f) const {   // every descriptor slot, used or not
+    for (int i = 0; i < kMaxDet; ++i) f(i);
+  }
+};
+
+FCAS_HD void setup_one(const NetDesc& net, const SegDesc& sg, const double* th, EvalDesc& ev) {
+  SkyFrame fr;
+  setup_point(net, th, ev.coef, fr);
+  for (int i = 0; i < net.n_det; ++i) setup_detector(net, sg, fr, i, ev);
+  ev.rank = setup_basis(ev, DetLoop{net.n_det});
 }
 
 // Common phase of bin k in cycles, b = (f_k / f*)^(-1/3): FP64 throughout.
