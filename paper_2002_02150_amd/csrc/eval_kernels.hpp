@@ -60,33 +60,33 @@ template <typename Real>
 constexpr int kLdsSeries = kJointExchange<Real> ? 2 : 1;
 
 // All stages of both series of one transform.
-template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF = false, bool WAVE = false>
+template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF, bool WAVE, int PAD>
 __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf0, cplx<Real>* buf1,
                                            const cplx<Real>* tw, int t) {
   if constexpr (I < Rad::count) {
     constexpr int R = Rad::value[I];
     constexpr bool LAST = (I == Rad::count - 1);
     if constexpr (kJointExchange<Real>) {
-      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[0], buf0, tw, t);
-      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[1], buf1, tw, t);
+      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[0], buf0, tw, t);
+      stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[1], buf1, tw, t);
       if constexpr (!LAST) {
         lds_exchange_sync<WAVE>();
-        stage_gather<Real, L, E>(v[0], buf0, t);
-        stage_gather<Real, L, E>(v[1], buf1, t);
+        stage_gather<Real, L, E, PAD>(v[0], buf0, t);
+        stage_gather<Real, L, E, PAD>(v[1], buf1, t);
         lds_exchange_sync<WAVE>();
       }
     } else {
 #pragma unroll
       for (int s = 0; s < 2; ++s) {
-        stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(v[s], buf0, tw, t);
+        stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[s], buf0, tw, t);
         if constexpr (!LAST) {
           lds_exchange_sync<WAVE>();
-          stage_gather<Real, L, E>(v[s], buf0, t);
+          stage_gather<Real, L, E, PAD>(v[s], buf0, t);
           lds_exchange_sync<WAVE>();
         }
       }
     }
-    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE>(v, buf0, buf1, tw, t);
+    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE, PAD>(v, buf0, buf1, tw, t);
   }
 }
 
@@ -101,7 +101,7 @@ __device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, con
 // LDS of the two passes: exchange buffers and twiddle tables.
 template <typename Real, class PL>
 struct PassLds {
-  static constexpr int LP1 = lds_padded_len(PL::N1), LP2 = lds_padded_len(PL::N2);
+  static constexpr int LP1 = lds_padded_len<kPad1>(PL::N1), LP2 = lds_padded_len<kPad2>(PL::N2);
   static constexpr int X1 = kLdsSeries<Real> * PL::C * LP1, X2 = kLdsSeries<Real> * PL::RW * LP2;
   static constexpr int X = X1 > X2 ? X1 : X2;
   static constexpr int TW = PL::N1 > PL::N2 ? PL::N1 : PL::N2;
@@ -132,7 +132,7 @@ __device__ __forceinline__ void pass1_body(PassArgs a, cplx<Real>* lds, const cp
       pass1_compute<Real, PL, DT>(v, d, a.evals[a.list[a.chunk_begin + slot]]);
       const int next = item + nblocks;
       if (next < items) pass1_fetch_item<Real, PL, DT>(d, a, next, c, p);
-      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, false, kPad1>(v, buf0, buf1, tw, p);
       pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
     }
   } else {
@@ -144,7 +144,7 @@ __device__ __forceinline__ void pass1_body(PassArgs a, cplx<Real>* lds, const cp
       const SegDesc& sg = a.segs[ev.seg];
       cplx<Real> v[2][PL::E1];
       pass1_prologue<Real, PL, 0>(v, ev, sg, a.n_det, tile, c, p);
-      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, buf0, buf1, tw, p);
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, false, kPad1>(v, buf0, buf1, tw, p);
       cplx<Real>* ws = (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N;
       pass1_store<Real, PL>(v, ws, tile, c, p);
     }
@@ -183,7 +183,7 @@ __device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const Pas
   // work-group barrier
   constexpr bool WAVE = (64 % PL::P2) == 0;
   pass2_twiddle<Real, PL>(v, tile, r, p);
-  run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE>(v, buf0, buf1, tw, p);
+  run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE, kPad2>(v, buf0, buf1, tw, p);
   const SegDesc& sg = a.segs[a.evals[e].seg];
   Real g;
   int j;
@@ -357,7 +357,7 @@ __device__ __forceinline__ void signal_count(int32_t* ctr) {
 template <typename Real, class PL>
 __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
   static_assert(PL::T1 == PL::T2, "the fused schedule needs equal work-item sizes");
-  constexpr int LP1 = lds_padded_len(PL::N1), LP2 = lds_padded_len(PL::N2);
+  constexpr int LP1 = lds_padded_len<kPad1>(PL::N1), LP2 = lds_padded_len<kPad2>(PL::N2);
   constexpr int LDSN = 2 * ((PL::C * LP1 > PL::RW * LP2) ? PL::C * LP1 : PL::RW * LP2);
   constexpr int NW = PL::T2 / 64;
   constexpr int T1 = PL::TILES1, T2 = PL::TILES2, T = T1 + T2;
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
       const int c = tid % PL::C, p = tid / PL::C;
       cplx<Real> v[2][PL::E1];
       pass1_prologue<Real, PL>(v, ev, sg, a.n_det, tile, c, p);
-      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(v, lds + c * LP1, lds + (PL::C + c) * LP1,
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, false, kPad1>(v, lds + c * LP1, lds + (PL::C + c) * LP1,
                                                                           tw1, p);
       pass1_store<Real, PL>(v, ws, tile, c, p);
       signal_count(f.done1 + ep);
@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
       const int p = tid % PL::P2, r = tid / PL::P2;
       cplx<Real> v[2][PL::E2];
       pass2_load<Real, PL>(v, ws, tile, r, p);
-      run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1>(v, lds + r * LP2, lds + (PL::RW + r) * LP2, tw2,
+      run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, false, kPad2>(v, lds + r * LP2, lds + (PL::RW + r) * LP2, tw2,
                                                                    p);
       const SegDesc& sg = a.segs[a.evals[e].seg];
       Real g;

@@ -291,10 +291,19 @@ struct Radices {
   }
 };
 
-// LDS index padding: one spare element every 16 breaks the power-of-two
-// strides of the stage writes across banks.
-FCAS_HD int lds_pad(int i) { return i + (i >> 4); }
-constexpr int lds_padded_len(int L) { return L + (L >> 4) + 1; }
+// LDS index padding: one spare element after every 2^S (S > 0) breaks the
+// power-of-two strides of the stage writes across banks; S = 0 leaves the
+// buffer unpadded.  Each pass takes the S measured fastest for it.
+template <int S>
+FCAS_HD int lds_pad(int i) {
+  if constexpr (S > 0) return i + (i >> S);
+  else return i;
+}
+template <int S>
+constexpr int lds_padded_len(int L) {
+  if constexpr (S > 0) return L + (L >> S) + 1;
+  else return L;
+}
 
 // position of output p of virtual thread v in stage with sub-length Ns, radix R
 FCAS_HD int stockham_dst(int v, int Ns, int R, int p) { return (v / Ns) * Ns * R + (v % Ns) + p * Ns; }

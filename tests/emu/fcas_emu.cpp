@@ -39,7 +39,7 @@ struct Regs {
 
 // All stages of a length-L transform for `nt` threads sharing one LDS buffer
 // per transform: buffer of thread `tid` is bufs[owner(tid)], index t = pos(tid).
-template <typename Real, int L, int E, class Rad, int I, int Ns, bool HALF, class Owner, class Pos>
+template <typename Real, int L, int E, class Rad, int I, int Ns, bool HALF, int PAD, class Owner, class Pos>
 static void emu_stages(std::vector<Regs<Real, E>>& regs, std::vector<std::vector<cplx<Real>>>& bufs,
                        const std::vector<cplx<Real>>& tw, Owner owner, Pos pos) {
   if constexpr (I < Rad::count) {
@@ -47,14 +47,14 @@ static void emu_stages(std::vector<Regs<Real, E>>& regs, std::vector<std::vector
     constexpr bool LAST = (I == Rad::count - 1);
     for (int s = 0; s < 2; ++s) {
       for (size_t tid = 0; tid < regs.size(); ++tid)
-        stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0>(regs[tid].v[s], bufs[owner(tid)].data(), tw.data(),
-                                                                  pos(tid));
+        stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(regs[tid].v[s], bufs[owner(tid)].data(),
+                                                                       tw.data(), pos(tid));
       if constexpr (!LAST) {
         for (size_t tid = 0; tid < regs.size(); ++tid)
-          stage_gather<Real, L, E>(regs[tid].v[s], bufs[owner(tid)].data(), pos(tid));
+          stage_gather<Real, L, E, PAD>(regs[tid].v[s], bufs[owner(tid)].data(), pos(tid));
       }
     }
-    emu_stages<Real, L, E, Rad, I + 1, Ns * R, false>(regs, bufs, tw, owner, pos);
+    emu_stages<Real, L, E, Rad, I + 1, Ns * R, false, PAD>(regs, bufs, tw, owner, pos);
   }
 }
 
@@ -78,13 +78,13 @@ static void run(const SegDesc& sg, const EvalDesc& ev, int n_det, std::vector<do
   std::vector<cplx<Real>> tw1(PL::N1), tw2(PL::N2);
   for (int m = 0; m < PL::N1; ++m) tw1[m] = twiddle<Real>(m, PL::N1);
   for (int m = 0; m < PL::N2; ++m) tw2[m] = twiddle<Real>(m, PL::N2);
-  const int LP1 = lds_padded_len(PL::N1), LP2 = lds_padded_len(PL::N2);
+  const int LP1 = lds_padded_len<kPad1>(PL::N1), LP2 = lds_padded_len<kPad2>(PL::N2);
   for (int tile = 0; tile < PL::TILES1; ++tile) {
     std::vector<Regs<Real, PL::E1>> regs(PL::T1);
     std::vector<std::vector<cplx<Real>>> bufs(PL::C, std::vector<cplx<Real>>(LP1));
     for (int tid = 0; tid < PL::T1; ++tid)
       prologue<Real, PL, DT>(regs[tid].v, ev, sg, n_det, tile, tid % PL::C, tid / PL::C);
-    emu_stages<Real, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true>(
+    emu_stages<Real, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, kPad1>(
         regs, bufs, tw1, [](size_t t) { return (int)(t % PL::C); }, [](size_t t) { return (int)(t / PL::C); });
     for (int tid = 0; tid < PL::T1; ++tid) pass1_store<Real, PL>(regs[tid].v, ws.data(), tile, tid % PL::C, tid / PL::C);
   }
@@ -96,7 +96,7 @@ static void run(const SegDesc& sg, const EvalDesc& ev, int n_det, std::vector<do
     std::vector<std::vector<cplx<Real>>> bufs(PL::RW, std::vector<cplx<Real>>(LP2));
     for (int tid = 0; tid < PL::T2; ++tid)
       pass2_load<Real, PL>(regs[tid].v, ws.data(), tile, tid / PL::P2, tid % PL::P2);
-    emu_stages<Real, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false>(
+    emu_stages<Real, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, kPad2>(
         regs, bufs, tw2, [](size_t t) { return (int)(t / PL::P2); }, [](size_t t) { return (int)(t % PL::P2); });
     for (int tid = 0; tid < PL::T2; ++tid) {
       const int r = tid / PL::P2, p = tid % PL::P2;
