@@ -34,7 +34,8 @@ import time
 import numpy as np
 import torch
 
-from . import Context, PsoConfig, Swarm, polish
+from . import Context
+from .campaign import search_segments
 from .params import chirp_times
 
 FS, F_LOW, F_HIGH = 2048.0, 30.0, 1000.0
@@ -77,8 +78,7 @@ def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, lo
         injections.append(inj)
     t_series = time.perf_counter() - t0
 
-    R = n_seg * RUNS
-    n = R * PARTICLES
+    n = n_seg * RUNS * PARTICLES
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo_box, box_hi=hi_box, max_batch=n,
                                max_segments=n_seg, max_samples=SEG)
     psd = torch.from_numpy(synth.psd_matrix(D, SEG, FS)).to(dev)
@@ -94,50 +94,10 @@ def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, lo
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t1
 
-    sw = Swarm(ctx, PsoConfig(n_runs=R, n_particles=PARTICLES, n_iter=iters, seed=20020215 + seed))
-    seg = (torch.arange(R, device=dev, dtype=torch.int32) // RUNS).repeat_interleave(PARTICLES)
-    f = torch.empty(n, dtype=torch.float64, device=dev)
-    j = torch.empty(n, dtype=torch.int32, device=dev)
-
-    def iteration():
-        ctx.eval(sw.theta, seg, f, j)
-        sw.step(f, j)
-
-    group = min(20, iters)
-    t2 = time.perf_counter()
-    sw.init()
-    st = torch.cuda.Stream()
-    st.wait_stream(torch.cuda.current_stream())
-    with torch.cuda.stream(st):
-        iteration()                       # iteration 1, eagerly, before the capture
-    torch.cuda.current_stream().wait_stream(st)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        for _ in range(group):
-            iteration()
-    graph1 = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph1):
-        iteration()
-    rest = iters - 1
-    for g in range(rest // group):
-        graph.replay()
-        if (g + 1) % 20 == 0:            # progress every 400 iterations (waits for the device)
-            torch.cuda.synchronize()
-            log(f"iteration {1 + (g + 1) * group}: {time.perf_counter() - t2:.1f} s")
-    for _ in range(rest % group):
-        graph1.replay()
-    # best run of every segment, then the polish of those points
-    best_f = sw.best_f.view(n_seg, RUNS)
-    k = torch.argmax(best_f, dim=1)
-    rows = torch.arange(n_seg, device=dev) * RUNS + k
-    span = torch.tensor(hi_box, dtype=torch.float64, device=dev) - torch.tensor(lo_box, dtype=torch.float64,
-                                                                                device=dev)
-    theta = (torch.tensor(lo_box, dtype=torch.float64, device=dev) + sw.best_x[rows] * span).contiguous()
-    seg_best = torch.arange(n_seg, device=dev, dtype=torch.int32)
-    f_pso = best_f.gather(1, k[:, None])[:, 0].clone()
-    theta, f_pol, j_pol = polish(ctx, theta, seg_best, steps=polish_steps, step_frac=1e-3, trials=16)
-    torch.cuda.synchronize()
-    t_run = time.perf_counter() - t2
+    res = search_segments(ctx, n_seg, RUNS, PARTICLES, iters, seed=20020215 + seed, polish_steps=polish_steps,
+                          log=log)
+    t_run = res["seconds"]
+    f_pso, f_pol, j_pol, theta = res["rho_sq_pso"], res["rho_sq"], res["argmax"], res["theta"]
     evaluated = ctx.evaluated()
 
     f_pso, f_pol, j_pol, theta = f_pso.cpu().numpy(), f_pol.cpu().numpy(), j_pol.cpu().numpy(), theta.cpu().numpy()

@@ -166,3 +166,16 @@ def test_full_search_small():
     for d in out["injections"]:
         assert d["rho_sq"] >= d["rho_sq_pso"] - 1e-9
         assert d["rho0_sq"] > 0
+
+
+def test_detection_study_small():
+    """The detection-statistics study (time-slid noise-only segments, injected
+    segments, one batched search, lognormal threshold, detection probability
+    and loss) runs end to end at a small size with consistent outputs."""
+    require_gpu()
+    from paper_2002_02150_amd.detection import run
+    out = run(slides=1, per_snr=2, snrs=(12.0,), iters=20, n_per_slide=4, log=lambda s: None)
+    assert out["segments_h0"] == 4 and out["segments_h1"] == 2
+    assert out["eta"] > out["h0_rho_quantiles"][0.5] > 0
+    row = out["table"][0]
+    assert 0.0 <= row["detection_probability"] <= 1.0 and row["median_rho0"] > 0
