@@ -98,19 +98,18 @@ __device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, con
   pass1_fetch<Real, PL, DT>(d, a.segs[ev.seg], item - slot * PL::TILES1, c, p);
 }
 
-// LDS of the two passes: exchange buffers and twiddle tables.
+// LDS exchange buffers of the two passes: padded length of one transform and
+// elements per work-group.
 template <typename Real, class PL>
 struct PassLds {
   static constexpr int LP1 = lds_padded_len<kPad1>(PL::N1), LP2 = lds_padded_len<kPad2>(PL::N2);
   static constexpr int X1 = kLdsSeries<Real> * PL::C * LP1, X2 = kLdsSeries<Real> * PL::RW * LP2;
-  static constexpr int X = X1 > X2 ? X1 : X2;
-  static constexpr int TW = PL::N1 > PL::N2 ? PL::N1 : PL::N2;
 };
 
 // Pass 1 on the items of `a` taken by work-group `block` of `nblocks`
 // (tw holds the length-N1 twiddles).
 template <typename Real, class PL, int DT>
-__device__ __forceinline__ void pass1_body(PassArgs a, cplx<Real>* lds, const cplx<Real>* tw, int block,
+__device__ __forceinline__ void pass1_body(const PassArgs& a, cplx<Real>* lds, const cplx<Real>* tw, int block,
                                            int nblocks) {
   constexpr int LP = PassLds<Real, PL>::LP1;
   const int tid = threadIdx.x;
@@ -214,7 +213,7 @@ __device__ __forceinline__ void pass2_fetch_item(cplx<Real> (&v)[2][PL::E2], con
 // Pass 2 on the items of `a` taken by work-group `block` of `nblocks` (tw holds
 // the length-N2 twiddles).
 template <typename Real, class PL>
-__device__ __forceinline__ void pass2_body(PassArgs a, cplx<Real>* lds, const cplx<Real>* tw, int block,
+__device__ __forceinline__ void pass2_body(const PassArgs& a, cplx<Real>* lds, const cplx<Real>* tw, int block,
                                            int nblocks) {
   constexpr int LP = PassLds<Real, PL>::LP2;
   const int tid = threadIdx.x;
