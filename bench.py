@@ -322,7 +322,7 @@ def run_gradient(a, torch, dev):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark measures one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
