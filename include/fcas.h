@@ -27,6 +27,9 @@
  *   - A segment id that is out of range or not registered is detected on the
  *     device: fitness NaN, argmax -2, and the context's device error flag is
  *     set (read it with fcas_device_error(), which synchronises).
+ *   - Results are bitwise repeatable: a point's fitness and argmax do not depend
+ *     on the batch, the order, the grid sizes, the workspace chunking or the
+ *     schedule it is evaluated with.
  */
 #ifndef FCAS_H
 #define FCAS_H
