@@ -8,7 +8,10 @@ search (2000 iterations) and ends with the best of the runs and the gradient
 polish of that point.  value = fitness evaluations of the
 particles per second over the timed region (inputs resident in HBM).  A second
 timed region launches the same steps eagerly with HIP events around the FFT
-pass kernels, for the roofline figures.
+pass kernels, for the roofline figures.  The FP64 oracle evaluates the first
+PSO batch on the host cores (cpu_baseline), and the library's results on the
+same points are compared with it (parity: relative error of the fitness,
+argmax agreement).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -168,11 +171,12 @@ def fp64_plain_rate(torch, net, xf, psd_d, thetas, dev):
 def _oracle_worker(args):
     from oracle import fitness as F
     seg, pos, ten, th = args
-    return [F.fitness(seg, pos, ten, t)[0] for t in th]
+    return [F.fitness(seg, pos, ten, t) for t in th]
 
 
 def cpu_baseline(xf_np, psd, net, thetas, sample):
-    """The FP64 oracle on the host cores, on the first `sample` points."""
+    """The FP64 oracle on the host cores, on the first `sample` points; also
+    returns the oracle's (fitness, argmax) of those points, in order."""
     import multiprocessing as mp
     from oracle import fitness as F
     seg = F.prepare_segment(xf_np, psd, FS, F_LOW, F_HIGH)
@@ -182,11 +186,34 @@ def cpu_baseline(xf_np, psd, net, thetas, sample):
     ctx = mp.get_context("fork")
     t = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        pool.map(_oracle_worker, [(seg, net.pos_m, net.tensor, c) for c in chunks if len(c)])
+        parts = pool.map(_oracle_worker, [(seg, net.pos_m, net.tensor, c) for c in chunks])
     dt = time.perf_counter() - t
+    ref = [None] * len(th)
+    for i, part in enumerate(parts):
+        ref[i::cores] = part
     return dict(value=len(th) / dt, unit="evals/s", cores=cores, kind="oracle",
                 sample=f"{len(th)} fitness evaluations of the first PSO batch (4 det x 131072 samples), "
-                       f"multiprocessing pool over {cores} host cores, {dt:.1f} s wall")
+                       f"multiprocessing pool over {cores} host cores, {dt:.1f} s wall"), seg, ref
+
+
+def parity(torch, ctx, seg, net, thetas, ref, dev):
+    """Error of the library's mixed path against the FP64 oracle on the same
+    points: largest relative error of the fitness, and the argmax samples that
+    differ (a differing sample counts as a near tie when the oracle's value
+    there is within 1e-4 of its maximum)."""
+    from oracle import fitness as F
+    th = torch.from_numpy(np.ascontiguousarray(thetas)).to(dev)
+    f, j = ctx.eval(th, torch.zeros(len(thetas), dtype=torch.int32, device=dev))
+    f, j = f.cpu().numpy(), j.cpu().numpy()
+    fo = np.array([r[0] for r in ref])
+    jo = np.array([r[1] for r in ref])
+    rel = np.abs(f - fo) / np.abs(fo)
+    differ = np.nonzero(j != jo)[0]
+    ties = sum(F.gamma2_at(seg, net.pos_m, net.tensor, thetas[k], int(j[k])) >= (1 - 1e-4) * fo[k] for k in differ)
+    return {"points": int(len(thetas)), "max_rel_err_fitness": float(rel.max()),
+            "mean_rel_err_fitness": float(rel.mean()), "argmax_differs": int(len(differ)),
+            "argmax_differs_near_tie": int(ties),
+            "max_argmax_delta": int(np.abs(j - jo).max()), "bar": "1e-4 relative; argmax equal or a near tie"}
 
 
 def run_batched(a, torch, dev):
@@ -430,8 +457,10 @@ def main():
         out["fp64_plain"] = {"value": rate64, "unit": "evals/s", "speedup": value / rate64,
                              "what": "same kernels in FP64, one evaluation per call, no graph"}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(xf.cpu().numpy(), psd_d.cpu().numpy(), net,
-                                           first_batch.cpu().numpy(), a.cpu_sample)
+        sample = first_batch.cpu().numpy()[:a.cpu_sample]
+        out["cpu_baseline"], oseg, ref = cpu_baseline(xf.cpu().numpy(), psd_d.cpu().numpy(), net, sample,
+                                                      a.cpu_sample)
+        out["parity"] = parity(torch, ctx, oseg, net, sample, ref, dev)
     ctx.close()
     if per_launch:
         out["eager_launch_points"] = per_launch
