@@ -42,11 +42,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=320)
+    ap.add_argument("--cpu-sample", type=int, default=1280,
+                    help="points the oracle evaluates for cpu_baseline (the first 320 also for parity)")
     ap.add_argument("--schedule", choices=("fused", "two-pass"), default="two-pass")
-    ap.add_argument("--config", choices=("search", "batched", "gradient"), default="search",
+    ap.add_argument("--config", choices=("search", "batched", "gradient", "sweep"), default="search",
                     help="search: the benchmark configuration (default); batched: 256 ragged segments, "
-                         "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source")
+                         "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source; "
+                         "sweep: fitness batches of 320 to 20480 points")
     ap.add_argument("--launch-counts", action="store_true",
                     help="record the points evaluated by each eager launch (adds a sync per step)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -64,7 +66,7 @@ def kernel_hash():
 SCHEDULES = {"fused": 0, "two-pass": 1}
 
 
-def make_workload(torch, dev, schedule):
+def make_workload(torch, dev, schedule, max_batch=RUNS * PARTICLES):
     import synth
     from paper_2002_02150_amd import Context
     from paper_2002_02150_amd.params import chirp_times
@@ -75,8 +77,7 @@ def make_workload(torch, dev, schedule):
     t0, t15 = chirp_times(inj["m1"], inj["m2"], F_LOW)
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi,
-                               max_batch=RUNS * PARTICLES, max_samples=N_SAMPLES,
-                               schedule=SCHEDULES[schedule])
+                               max_batch=max_batch, max_samples=N_SAMPLES, schedule=SCHEDULES[schedule])
     xf = torch.from_numpy(noise).to(dev)
     psd_d = torch.from_numpy(np.ascontiguousarray(psd)).to(dev)
     ctx.inject(xf, psd_d, inj["alpha"], inj["delta"], t0, t15, inj["psi"], inj["phi_c"], inj["cos_iota"],
@@ -168,32 +169,50 @@ def fp64_plain_rate(torch, net, xf, psd_d, thetas, dev):
     return len(rows) / dt
 
 
-def _oracle_worker(args):
+_ORACLE = {}
+
+
+def _oracle_init(seg, pos, ten):
+    from threadpoolctl import threadpool_limits
+    _ORACLE.update(seg=seg, pos=pos, ten=ten, limits=threadpool_limits(1))   # one thread per process
+
+
+def _oracle_worker(th):
     from oracle import fitness as F
-    seg, pos, ten, th = args
-    return [F.fitness(seg, pos, ten, t) for t in th]
+    return [F.fitness(_ORACLE["seg"], _ORACLE["pos"], _ORACLE["ten"], t) for t in th]
+
+
+def _oracle_ready(_):
+    return True
 
 
 def cpu_baseline(xf_np, psd, net, thetas, sample):
-    """The FP64 oracle on the host cores, on the first `sample` points; also
-    returns the oracle's (fitness, argmax) of those points, in order."""
+    """The FP64 oracle on the host cores: a pool of one process per core (the
+    segment handed over once, the pool started before timing) evaluates
+    `sample` points uniform in the rectangle (the first PSO batch, then more
+    points drawn the same way).  Returns the rate, the oracle's segment and its
+    (fitness, argmax) of the first len(thetas) points, in order."""
     import multiprocessing as mp
+    import synth
     from oracle import fitness as F
     seg = F.prepare_segment(xf_np, psd, FS, F_LOW, F_HIGH)
-    th = thetas[:sample]
+    extra = synth.uniform_in_box(np.random.default_rng(synth.seed_sequence(2, 0, 3000)), max(0, sample - len(thetas)),
+                                 synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI)
+    th = np.concatenate([thetas, extra])[:sample]
     cores = max(1, min(os.cpu_count() or 1, 64))
-    chunks = [th[i::cores] for i in range(cores)]
     ctx = mp.get_context("fork")
-    t = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        parts = pool.map(_oracle_worker, [(seg, net.pos_m, net.tensor, c) for c in chunks])
-    dt = time.perf_counter() - t
+    with ctx.Pool(cores, initializer=_oracle_init, initargs=(seg, net.pos_m, net.tensor)) as pool:
+        pool.map(_oracle_ready, range(cores))
+        t = time.perf_counter()
+        parts = pool.map(_oracle_worker, [th[i::cores] for i in range(cores)])
+        dt = time.perf_counter() - t
     ref = [None] * len(th)
     for i, part in enumerate(parts):
         ref[i::cores] = part
     return dict(value=len(th) / dt, unit="evals/s", cores=cores, kind="oracle",
-                sample=f"{len(th)} fitness evaluations of the first PSO batch (4 det x 131072 samples), "
-                       f"multiprocessing pool over {cores} host cores, {dt:.1f} s wall"), seg, ref
+                sample=f"{len(th)} fitness evaluations uniform in the rectangle (the first PSO batch and more "
+                       f"drawn alike; 4 det x 131072 samples), one single-threaded process per host core, {dt:.1f} s wall"), \
+        seg, ref[:len(thetas)]
 
 
 def parity(torch, ctx, seg, net, thetas, ref, dev):
@@ -346,6 +365,50 @@ def run_gradient(a, torch, dev):
     print(json.dumps(out))
 
 
+def run_sweep(a, torch, dev):
+    """Fitness batches of n points uniform in the rectangle (every point
+    evaluated) on the benchmark segment, n = 320 ... 20480: evals/s per batch
+    size, each batch one fitness_eval_batch call replayed from a HIP graph."""
+    import synth
+    ctx, net, xf, psd_d, inj = make_workload(torch, dev, a.schedule, max_batch=20480)
+    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    rng = np.random.default_rng(synth.seed_sequence(2, 0, 2000))
+    rows = []
+    for n in (320, 1280, 5120, 20480):
+        th = torch.from_numpy(synth.uniform_in_box(rng, n, lo, hi)).to(dev)
+        seg = torch.zeros(n, dtype=torch.int32, device=dev)
+        f = torch.empty(n, dtype=torch.float64, device=dev)
+        j = torch.empty(n, dtype=torch.int32, device=dev)
+        for _ in range(max(a.warmup, 1)):
+            ctx.eval(th, seg, f, j)
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            ctx.eval(th, seg, f, j)
+        torch.cuda.current_stream().wait_stream(st)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            ctx.eval(th, seg, f, j)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(a.steps):
+            g.replay()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        rows.append({"batch": n, "evals_per_s": a.steps * n / dt, "ms_per_call": dt / a.steps * 1e3,
+                     "hbm_alg_tb_per_s": a.steps * n * 32 * N_SAMPLES / dt / 1e12})
+    ctx.close()
+    out = {"metric": "coherent-fitness evals/s by batch size, 4 det x 131072 samples",
+           "value": max(r["evals_per_s"] for r in rows), "unit": "evals/s", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+f64phase", "data": "synthetic",
+           "config": {"workload": "batches of 320 to 20480 points uniform in the rectangle on the 4-detector, "
+                                  "64-s, SNR-10 benchmark segment; one step = one fitness_eval_batch call "
+                                  "(a captured HIP graph)", "parallelism": "single-gpu"},
+           "sweep": rows}
+    print(json.dumps(out))
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -358,11 +421,13 @@ def main():
     from paper_2002_02150_amd import PsoConfig, Swarm
     dev = torch.device("cuda", 0)
     if a.steps is None:
-        a.steps = {"search": 2000, "batched": 20, "gradient": 50}[a.config]
+        a.steps = {"search": 2000, "batched": 20, "gradient": 50, "sweep": 20}[a.config]
     if a.config == "batched":
         return run_batched(a, torch, dev)
     if a.config == "gradient":
         return run_gradient(a, torch, dev)
+    if a.config == "sweep":
+        return run_sweep(a, torch, dev)
     ctx, net, xf, psd_d, inj = make_workload(torch, dev, a.schedule)
     sw = Swarm(ctx, PsoConfig(n_runs=RUNS, n_particles=PARTICLES, n_iter=2000, seed=20020215))
     first_batch = sw.init().clone()
@@ -457,10 +522,18 @@ def main():
         out["fp64_plain"] = {"value": rate64, "unit": "evals/s", "speedup": value / rate64,
                              "what": "same kernels in FP64, one evaluation per call, no graph"}
     if not a.no_cpu_baseline:
-        sample = first_batch.cpu().numpy()[:a.cpu_sample]
+        sample = first_batch.cpu().numpy()
         out["cpu_baseline"], oseg, ref = cpu_baseline(xf.cpu().numpy(), psd_d.cpu().numpy(), net, sample,
                                                       a.cpu_sample)
         out["parity"] = parity(torch, ctx, oseg, net, sample, ref, dev)
+        from oracle import fitness as F
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(1):
+            t1 = time.perf_counter()
+            for t_ in sample[:8]:
+                F.fitness(oseg, net.pos_m, net.tensor, t_)
+            out["cpu_baseline_1core"] = {"value": 8 / (time.perf_counter() - t1), "unit": "evals/s", "cores": 1,
+                                         "kind": "oracle", "sample": "8 points of the first PSO batch, one thread"}
     ctx.close()
     if per_launch:
         out["eager_launch_points"] = per_launch
