@@ -57,8 +57,8 @@ extern "C" {
                          projection and maximum in FP32                           */
 #define FCAS_FP64 1   /* everything in FP64 (the plain reference path)            */
 
-/* launch schedule of the two FFT passes (FUSED: FCAS_MIXED only; an FCAS_FP64
- * context runs TWO_PASS) */
+/* launch schedule of the FFT passes (FUSED: FCAS_MIXED only; an FCAS_FP64
+ * context runs TWO_PASS, and so do the three-pass plans under FUSED) */
 #define FCAS_SCHEDULE_FUSED 0     /* one persistent launch per plan, passes pipelined  */
 #define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk
                                      (the faster one on MI355X: recommended)          */
@@ -104,20 +104,26 @@ int fcas_destroy(fcas_ctx* ctx);
 /* Bytes of FFT workspace owned by the context. */
 size_t fcas_workspace_bytes(const fcas_ctx* ctx);
 
-/* 1 if a segment of n samples has an FFT plan, else 0 (host only, no device). */
+/* 1 if a segment of n samples has an FFT plan, else 0 (host only, no device).
+ * Supported: 2^k for 2^11 <= n <= 2^18, 3 * 2^k for 2^13 <= n / 3 <= 2^16, and
+ * 2^k * 225 for k = 11, 14, 15 (225 s, 30 min and one hour at 2048 Hz). */
 int fcas_supported_n(int64_t n_samples);
 
 /* FFT plans.  A plan splits N = N1 N2 into N1-point column transforms (pass 1,
  * E1 elements per thread, `cols` columns per work-group) and N2-point row
  * transforms (pass 2, E2 elements per thread, `rows` rows per work-group);
- * several plans may serve one length.  fcas_plan_info reports plan `plan`
- * (float figures; host only, any output may be NULL). */
+ * several plans may serve one length.  The 2^k * 225 lengths run three
+ * passes, N = N1 * 225 * N2', with 225-point transforms between the two: for
+ * them `n2` reports the 225 N2' columns of pass 1 and `e2`, `rows` describe
+ * the N2'-point last pass.  fcas_plan_info reports plan `plan` (float
+ * figures; host only, any output may be NULL). */
 int fcas_plan_count(void);
 int fcas_plan_info(int32_t plan, int64_t* n_samples, int32_t* n1, int32_t* n2, int32_t* e1, int32_t* e2,
                    int32_t* cols, int32_t* rows);
 
 /* Use plan `plan` for segments of its length registered after this call, with
- * grid1 / grid2 persistent work-groups for its two passes (0 = default).
+ * grid1 / grid2 persistent work-groups for its first and last passes (grid2
+ * also sizes a three-pass plan's middle pass; 0 = default).
  * This is how the autotuner's choice is applied.  FCAS_EINVAL for a plan out
  * of range or grid sizes outside [0, 2^20]. */
 int fcas_select_plan(fcas_ctx* ctx, int32_t plan, int32_t grid1, int32_t grid2);
@@ -252,8 +258,9 @@ int fcas_evaluated(fcas_ctx* ctx, uint64_t* count_out);
 int fcas_set_timing(fcas_ctx* ctx, int enable);
 
 /* Synchronises and returns the summed duration (ms) and launch count of the
- * FFT kernel named `which` ("pass1", "pass2" of the two-pass schedule, "fused"
- * of the fused schedule) since timing was enabled; resets the counters. */
+ * FFT kernel named `which` ("pass1", "pass2" of the two-pass schedule,
+ * "passm" for the middle pass of three-pass plans, "fused" of the fused
+ * schedule) since timing was enabled; resets the counters. */
 int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t* launches);
 
 /* Message of the last failure on the calling thread ("" if none). */

@@ -27,6 +27,18 @@ hipError_t launch_pass1_f32(int plan, const PassArgs& a, int grid, hipStream_t s
   return hipGetLastError();
 }
 
+#define FCAS_CASE_PM(id, ...) \
+  case id:                    \
+    return launch_passm_plan<float, PlanF##id>(a, grid, s);
+
+hipError_t launch_passm_f32(int plan, const PassArgs& a, int grid, hipStream_t s) {
+  switch (plan) {
+    FCAS_PLAN_LIST(FCAS_CASE_PM)
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s) {
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_CASE_P2)
@@ -36,14 +48,12 @@ hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s
   return hipGetLastError();
 }
 
-#define FCAS_CASE_FUSED(id, ...)                                                                \
-  case id:                                                                                       \
-    hipLaunchKernelGGL((k_fused<float, PlanF##id>), dim3(grid), dim3(PlanF##id::T1), 0, s, f);   \
-    break;
-#define FCAS_CASE_OCC(id, ...)                                                                              \
-  case id:                                                                                                   \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_fused<float, PlanF##id>, PlanF##id::T1, 0); \
-    break;
+#define FCAS_CASE_FUSED(id, ...) \
+  case id:                       \
+    return launch_fused_plan<PlanF##id>(f, grid, s);
+#define FCAS_CASE_OCC(id, ...) \
+  case id:                     \
+    return fused_occupancy_plan<PlanF##id>();
 
 hipError_t launch_fused_f32(int plan, const FusedArgs& f, int grid, hipStream_t s) {
   switch (plan) {
@@ -51,27 +61,25 @@ hipError_t launch_fused_f32(int plan, const FusedArgs& f, int grid, hipStream_t 
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
-// Work-groups of the fused kernel of `plan` that one compute unit holds at once.
+// Work-groups of the fused kernel of `plan` that one compute unit holds at
+// once (0 for three-pass plans, which have no fused kernel).
 int fused_blocks_per_cu(int plan) {
-  int nb = 0;
-  hipError_t e = hipErrorInvalidValue;
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_CASE_OCC)
     default:
       return 0;
   }
-  return e == hipSuccess ? nb : 0;
 }
 
 hipError_t launch_finalize_f32(const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                                  const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
-                                  unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
+                                  const int32_t* part_j, int n, int part_stride, const int32_t* plan_parts2,
+                                  int32_t* counts, unsigned long long* evaluated, double* fitness, int32_t* argmax,
+                                  hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize<float>, dim3((n + 3) / 4), dim3(256), 0, s, evals, segs,
-                     (const float*)part_g, part_j, n, plan_parts2, counts, evaluated, fitness, argmax);
+                     (const float*)part_g, part_j, n, part_stride, plan_parts2, counts, evaluated, fitness, argmax);
   return hipGetLastError();
 }
 

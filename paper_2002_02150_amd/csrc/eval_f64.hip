@@ -27,6 +27,18 @@ hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s
   return hipGetLastError();
 }
 
+#define FCAS_CASE_PM(id, ...) \
+  case id:                    \
+    return launch_passm_plan<double, PlanD##id>(a, grid, s);
+
+hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
+  switch (plan) {
+    FCAS_PLAN_LIST(FCAS_CASE_PM)
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
 hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_CASE_P2)
@@ -37,11 +49,12 @@ hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s
 }
 
 hipError_t launch_finalize_f64(const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                                  const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
-                                  unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
+                                  const int32_t* part_j, int n, int part_stride, const int32_t* plan_parts2,
+                                  int32_t* counts, unsigned long long* evaluated, double* fitness, int32_t* argmax,
+                                  hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize<double>, dim3((n + 3) / 4), dim3(256), 0, s, evals, segs,
-                     (const double*)part_g, part_j, n, plan_parts2, counts, evaluated, fitness, argmax);
+                     (const double*)part_g, part_j, n, part_stride, plan_parts2, counts, evaluated, fitness, argmax);
   return hipGetLastError();
 }
 

@@ -15,8 +15,9 @@ struct PassArgs {
   const int32_t* list;     // evaluation indices of this plan, in list order
   const int32_t* count;    // number of entries in `list`
   void* ws;                // workspace: cap slots of 2 N complex
-  void* part_g;            // [max_batch][kMaxParts2] partial maxima (Real)
-  int32_t* part_j;         // [max_batch][kMaxParts2] their samples
+  void* part_g;            // [max_batch][part_stride] partial maxima (Real)
+  int32_t* part_j;         // [max_batch][part_stride] their samples
+  int32_t part_stride;     // partials per evaluation slot (>= the plan's PARTS2)
   int32_t n_det;
   int32_t chunk_begin;     // first list position handled by this launch
   int32_t cap;             // workspace slots (positions per launch)
@@ -165,6 +166,66 @@ __global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))
 }
 
 // ---------------------------------------------------------------------------
+// Middle pass of the three-pass plans: length-NM transforms over the pass-1
+// output, in place (see Plan).  Each work item takes CM adjacent columns of
+// one pass-1 row, so every load and store instruction moves CM * 8 bytes of
+// contiguous row per transform element (128 bytes at CM = 16).
+// ---------------------------------------------------------------------------
+template <typename Real, class PL>
+__device__ __forceinline__ void passm_fetch_item(cplx<Real> (&v)[2][PL::EM], const PassArgs& a, int item, int c,
+                                                 int p) {
+  const int slot = item / PL::TILESM;
+  passm_fetch<Real, PL>(v, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, item - slot * PL::TILESM, c, p);
+}
+
+template <typename Real, class PL>
+__device__ __forceinline__ void passm_item(cplx<Real> (&v)[2][PL::EM], const PassArgs& a, int item,
+                                           cplx<Real>* buf0, cplx<Real>* buf1, const cplx<Real>* tw, int c, int p) {
+  const int slot = item / PL::TILESM;
+  const int tile = item - slot * PL::TILESM;
+  passm_twiddle_in<Real, PL>(v, tile, c, p);
+  run_stages<Real, PL, PL::NM, PL::EM, typename PL::RadM, 0, 1, false, false, kPadM>(v, buf0, buf1, tw, p);
+  passm_twiddle_out<Real, PL>(v, tile, c, p);
+  passm_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
+}
+
+// Middle pass on the items of `a` taken by work-group `block` of `nblocks`,
+// with the next item's loads in flight while one is transformed (two register
+// sets).  Items cover disjoint workspace elements, so a prefetch never reads
+// what another item stores.
+template <typename Real, class PL>
+__device__ __forceinline__ void passm_body(const PassArgs& a, cplx<Real>* lds, const cplx<Real>* tw, int block,
+                                           int nblocks) {
+  constexpr int LP = lds_padded_len<kPadM>(PL::NM);
+  const int tid = threadIdx.x;
+  const int items = launch_span(a) * PL::TILESM;
+  const int c = tid % PL::CM, p = tid / PL::CM;
+  cplx<Real>* buf0 = lds + c * LP;
+  cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::CM + c) * LP : buf0;
+  cplx<Real> va[2][PL::EM], vb[2][PL::EM];
+  int item = block;
+  if (item < items) passm_fetch_item<Real, PL>(va, a, item, c, p);
+  while (item < items) {
+    const int next = item + nblocks;
+    if (next < items) passm_fetch_item<Real, PL>(vb, a, next, c, p);
+    passm_item<Real, PL>(va, a, item, buf0, buf1, tw, c, p);
+    if (next >= items) break;
+    item = next + nblocks;
+    if (item < items) passm_fetch_item<Real, PL>(va, a, item, c, p);
+    passm_item<Real, PL>(vb, a, next, buf0, buf1, tw, c, p);
+  }
+}
+
+template <typename Real, class PL>
+__global__ void __launch_bounds__(PL::TM) k_passm(PassArgs a) {
+  static_assert(PL::THREE, "two-pass plans have no middle pass");
+  __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::CM * lds_padded_len<kPadM>(PL::NM)];
+  __shared__ cplx<Real> tw[PL::NM];
+  init_twiddles<Real, PL::NM, PL::TM>(tw);
+  passm_body<Real, PL>(a, lds, tw, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
 // Pass 2: length-N2 row FFTs, |a_0|^2 + |a_1|^2 and its maximum over the rows
 // of one work item -> one partial (value, sample) per wavefront.  When every
 // row transform lies inside one wavefront the items need no work-group
@@ -181,7 +242,7 @@ __device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const Pas
   // row transforms held by one wavefront exchange through LDS without a
   // work-group barrier
   constexpr bool WAVE = (64 % PL::P2) == 0;
-  pass2_twiddle<Real, PL>(v, tile, r, p);
+  if constexpr (!PL::THREE) pass2_twiddle<Real, PL>(v, tile, r, p);
   run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE, kPad2>(v, buf0, buf1, tw, p);
   const SegDesc& sg = a.segs[a.evals[e].seg];
   Real g;
@@ -197,7 +258,7 @@ __device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const Pas
     }
   }
   if (lane == 0) {
-    const int64_t o = (int64_t)e * kMaxParts2 + tile * NW + wave;
+    const int64_t o = (int64_t)e * a.part_stride + tile * NW + wave;
     ((Real*)a.part_g)[o] = g;
     a.part_j[o] = j;
   }
@@ -252,7 +313,7 @@ __global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
 template <typename Real>
 __global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ evals,
                                                   const SegDesc* __restrict__ segs, const Real* __restrict__ part_g,
-                                                  const int32_t* __restrict__ part_j, int n,
+                                                  const int32_t* __restrict__ part_j, int n, int part_stride,
                                                   const int32_t* __restrict__ plan_parts2,
                                                   int32_t* __restrict__ counts,
                                                   unsigned long long* __restrict__ evaluated,
@@ -283,8 +344,8 @@ __global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ e
   Real g = (Real)-1;
   int j = 0x7fffffff;
   for (int t = lane; t < nt; t += 64) {
-    const Real go = part_g[(int64_t)e * kMaxParts2 + t];
-    const int jo = part_j[(int64_t)e * kMaxParts2 + t];
+    const Real go = part_g[(int64_t)e * part_stride + t];
+    const int jo = part_j[(int64_t)e * part_stride + t];
     if (better(go, jo, g, j)) {
       g = go;
       j = jo;
@@ -356,6 +417,7 @@ __device__ __forceinline__ void signal_count(int32_t* ctr) {
 template <typename Real, class PL>
 __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
   static_assert(PL::T1 == PL::T2, "the fused schedule needs equal work-item sizes");
+  static_assert(!PL::THREE, "the fused schedule covers two-pass plans");
   constexpr int LP1 = lds_padded_len<kPad1>(PL::N1), LP2 = lds_padded_len<kPad2>(PL::N2);
   constexpr int LDSN = 2 * ((PL::C * LP1 > PL::RW * LP2) ? PL::C * LP1 : PL::RW * LP2);
   constexpr int NW = PL::T2 / 64;
@@ -407,7 +469,7 @@ __global__ void __launch_bounds__(PL::T1) k_fused(FusedArgs f) {
         if (better(go, jo, g, j)) { g = go; j = jo; }
       }
       if (lane == 0) {
-        const int64_t o = (int64_t)e * kMaxParts2 + tile * NW + wave;
+        const int64_t o = (int64_t)e * a.part_stride + tile * NW + wave;
         ((Real*)a.part_g)[o] = g;
         a.part_j[o] = j;
       }

@@ -58,9 +58,10 @@ struct fcas_ctx {
   EvalDesc* d_evals = nullptr;
   int32_t* d_lists = nullptr;    // [kNumPlans][max_batch]
   int32_t* d_counts = nullptr;   // [kNumPlans]
-  void* d_part_g = nullptr;      // [max_batch][kMaxParts2]
+  void* d_part_g = nullptr;      // [max_batch][part_stride]
   int32_t* d_part_j = nullptr;
   int32_t* d_plan_parts2 = nullptr;
+  int part_stride = 1;           // pass-2 partials per point: the most any admitted plan leaves
   int32_t* d_err = nullptr;
   unsigned long long* d_evaluated = nullptr;   // running total of points evaluated
   double* d_sigma2 = nullptr;    // [FCAS_MAX_DET] scratch for segment registration
@@ -78,7 +79,7 @@ struct fcas_ctx {
   int fused_cap[kNumPlans] = {0};   // resident work-groups of each fused kernel (0 = not queried)
   int32_t* d_done = nullptr;        // [kNumPlans][2][max_batch] fused-schedule tile counters
   bool timing = false;
-  std::vector<TimedPair> t_pass1, t_pass2, t_fused;
+  std::vector<TimedPair> t_pass1, t_passm, t_pass2, t_fused;
   int grid1[kNumPlans], grid2[kNumPlans];   // persistent grid sizes of the two passes
   int chosen[kNumPlans];                     // plan used for new segments of each length (by default plan)
 };
@@ -155,6 +156,7 @@ int free_all(fcas_ctx* c) {
   for (void* p : bufs) if (p) hipFree(p);
   free_grad_buffers(c->grad);
   for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
+  for (auto& t : c->t_passm) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_pass2) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   for (auto& t : c->t_fused) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
   return FCAS_OK;
@@ -260,12 +262,14 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
   c->seg_y.assign(cfg->max_segments, nullptr);
   c->seg_b.assign(cfg->max_segments, nullptr);
   const size_t part_elt = c->prec ? 8 : 4;
+  for (int i = 0; i < kNumPlans; ++i)
+    if (kPlans[i].n <= cfg->max_samples) c->part_stride = std::max(c->part_stride, kPlans[i].parts2[c->prec]);
   if ((rc = dev_alloc(&c->d_net, sizeof(NetDesc))) || (rc = dev_alloc(&c->d_segs, sizeof(SegDesc) * cfg->max_segments)) ||
       (rc = dev_alloc(&c->d_evals, sizeof(EvalDesc) * B)) ||
       (rc = dev_alloc(&c->d_lists, sizeof(int32_t) * (size_t)kNumPlans * B)) ||
       (rc = dev_alloc(&c->d_counts, sizeof(int32_t) * kNumPlans)) ||
-      (rc = dev_alloc(&c->d_part_g, part_elt * (size_t)B * kMaxParts2)) ||
-      (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * kMaxParts2)) ||
+      (rc = dev_alloc(&c->d_part_g, part_elt * (size_t)B * c->part_stride)) ||
+      (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * c->part_stride)) ||
       (rc = dev_alloc(&c->d_plan_parts2, sizeof(int32_t) * kNumPlans)) ||
       (rc = dev_alloc(&c->d_err, sizeof(int32_t))) || (rc = dev_alloc(&c->d_sigma2, sizeof(double) * FCAS_MAX_DET)) ||
       (rc = dev_alloc(&c->d_ws, ws)) || (rc = alloc_grad_buffers(c->grad, B, net->n_det)) ||
@@ -425,7 +429,9 @@ hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t 
     hipEventCreate(&tp.b);
     hipEventRecord(tp.a, s);
   }
-  hipError_t e = pass == 1 ? launch_pass1(ctx->prec, plan, a, grid, s) : launch_pass2(ctx->prec, plan, a, grid, s);
+  hipError_t e = pass == 1   ? launch_pass1(ctx->prec, plan, a, grid, s)
+                 : pass == 3 ? launch_passm(ctx->prec, plan, a, grid, s)
+                             : launch_pass2(ctx->prec, plan, a, grid, s);
   if (ctx->timing) {
     hipEventRecord(tp.b, s);
     rec.push_back(tp);
@@ -454,6 +460,7 @@ PassArgs pass_args(fcas_ctx* ctx, int plan, int cap) {
   a.ws = ctx->d_ws;
   a.part_g = ctx->d_part_g;
   a.part_j = ctx->d_part_j;
+  a.part_stride = ctx->part_stride;
   a.n_det = ctx->net.n_det;
   a.chunk_begin = 0;
   a.cap = cap;
@@ -499,7 +506,9 @@ int enqueue_fused(fcas_ctx* ctx, int plan, int n, int cap, hipStream_t s) {
   return e == hipSuccess ? FCAS_OK : hip_fail(e, "fused launch");
 }
 
-// Enqueues set-up, both FFT passes of every plan in use, and finalize.
+// Enqueues set-up, the FFT passes of every plan in use, and finalize.  Plans
+// with a middle pass always run as separate launches (the fused schedule
+// covers two-pass plans).
 int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
                  int32_t* d_argmax, hipStream_t s) {
   hipError_t e;
@@ -514,7 +523,7 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
     const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
     int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
     if (cap < 1) cap = 1;
-    if (ctx->schedule == FCAS_SCHEDULE_FUSED) {
+    if (ctx->schedule == FCAS_SCHEDULE_FUSED && pi.nm == 1) {
       if ((rc = enqueue_fused(ctx, plan, n, cap, s))) return rc;
       continue;
     }
@@ -525,11 +534,17 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
       const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
       const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
       if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
+      if (pi.nm > 1) {
+        const int gm = std::min(m * pi.tilesm[ctx->prec], ctx->grid2[plan]);
+        if ((e = timed_launch(ctx, ctx->t_passm, s, 3, plan, a, gm)) != hipSuccess)
+          return hip_fail(e, "middle-pass launch");
+      }
       if ((e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
     }
   }
-  if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->d_plan_parts2,
-                           ctx->d_counts, ctx->d_evaluated, d_fitness, d_argmax, s)) != hipSuccess)
+  if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->part_stride,
+                           ctx->d_plan_parts2, ctx->d_counts, ctx->d_evaluated, d_fitness, d_argmax, s)) !=
+      hipSuccess)
     return hip_fail(e, "finalize launch");
   return FCAS_OK;
 }
@@ -646,9 +661,10 @@ int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t
   if (!ctx || !which || !total_ms || !launches) return fail(FCAS_EINVAL, "NULL argument");
   std::vector<TimedPair>* rec = nullptr;
   if (!std::strcmp(which, "pass1")) rec = &ctx->t_pass1;
+  else if (!std::strcmp(which, "passm")) rec = &ctx->t_passm;
   else if (!std::strcmp(which, "pass2")) rec = &ctx->t_pass2;
   else if (!std::strcmp(which, "fused")) rec = &ctx->t_fused;
-  else return fail(FCAS_EINVAL, "unknown kernel name '%s' (timed: pass1, pass2, fused)", which);
+  else return fail(FCAS_EINVAL, "unknown kernel name '%s' (timed: pass1, passm, pass2, fused)", which);
   hipSetDevice(ctx->device);
   double tot = 0.0;
   for (auto& t : *rec) {
@@ -672,26 +688,32 @@ int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t
 namespace fcas {
 hipError_t launch_pass1_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_passm_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_finalize_f32(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
+hipError_t launch_finalize_f32(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, int, const int32_t*,
                                int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
-hipError_t launch_finalize_f64(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, const int32_t*,
+hipError_t launch_finalize_f64(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, int, const int32_t*,
                                int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
   return precision ? launch_pass1_f64(plan, a, grid, s) : launch_pass1_f32(plan, a, grid, s);
 }
+hipError_t launch_passm(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
+  return precision ? launch_passm_f64(plan, a, grid, s) : launch_passm_f32(plan, a, grid, s);
+}
 hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
   return precision ? launch_pass2_f64(plan, a, grid, s) : launch_pass2_f32(plan, a, grid, s);
 }
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                           const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
-                           unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s) {
-  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, plan_parts2, counts, evaluated, fitness,
-                                         argmax, s)
-                   : launch_finalize_f32(evals, segs, part_g, part_j, n, plan_parts2, counts, evaluated, fitness,
-                                         argmax, s);
+                           const int32_t* part_j, int n, int part_stride, const int32_t* plan_parts2,
+                           int32_t* counts, unsigned long long* evaluated, double* fitness, int32_t* argmax,
+                           hipStream_t s) {
+  return precision ? launch_finalize_f64(evals, segs, part_g, part_j, n, part_stride, plan_parts2, counts, evaluated,
+                                         fitness, argmax, s)
+                   : launch_finalize_f32(evals, segs, part_g, part_j, n, part_stride, plan_parts2, counts, evaluated,
+                                         fitness, argmax, s);
 }
 }  // namespace fcas
 

@@ -149,6 +149,48 @@ FCAS_HD void dft3(cplx<T>& x0, cplx<T>& x1, cplx<T>& x2) {
   x2 = mk<T>(m.x + h * d.y, m.y - h * d.x);
 }
 
+// w = e^{+2 pi i/5}: X[j] = x0 + sum_{p=1..4} x_p w^{pj}.  The conjugate pairs
+// (x1, x4) and (x2, x3) enter through their sums (real parts of w^p) and
+// differences (imaginary parts).
+template <typename T>
+FCAS_HD void dft5(cplx<T>* x) {
+  const T c1 = (T)0.30901699437494742410, c2 = (T)-0.80901699437494742410;   // cos(2 pi/5), cos(4 pi/5)
+  const T s1 = (T)0.95105651629515357212, s2 = (T)0.58778525229247312917;    // sin(2 pi/5), sin(4 pi/5)
+  const cplx<T> t1 = add(x[1], x[4]), t2 = add(x[2], x[3]), t3 = sub(x[1], x[4]), t4 = sub(x[2], x[3]);
+  const cplx<T> a1 = mk<T>(x[0].x + c1 * t1.x + c2 * t2.x, x[0].y + c1 * t1.y + c2 * t2.y);
+  const cplx<T> a2 = mk<T>(x[0].x + c2 * t1.x + c1 * t2.x, x[0].y + c2 * t1.y + c1 * t2.y);
+  const cplx<T> b1 = mk<T>(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y);
+  const cplx<T> b2 = mk<T>(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y);
+  x[0] = add(x[0], add(t1, t2));
+  x[1] = add(a1, mul_i(b1));
+  x[4] = sub(a1, mul_i(b1));
+  x[2] = add(a2, mul_i(b2));
+  x[3] = sub(a2, mul_i(b2));
+}
+
+// 15 = 3 x 5 by the prime-factor (Good-Thomas) algorithm, which needs no
+// twiddle factors: input n = (5 n1 + 3 n2) mod 15 and output
+// k = (10 k1 + 6 k2) mod 15 (the CRT map; 10 = 1 mod 3, 6 = 1 mod 5) give
+// w15^{nk} = w3^{n1 k1} w5^{n2 k2}.  Five 3-point transforms over n1, then
+// three 5-point transforms over n2.
+template <typename T>
+FCAS_HD void dft15(cplx<T>* x) {
+  cplx<T> y[5][3];
+#pragma unroll
+  for (int n2 = 0; n2 < 5; ++n2) {
+    cplx<T> a0 = x[(3 * n2) % 15], a1 = x[(5 + 3 * n2) % 15], a2 = x[(10 + 3 * n2) % 15];
+    dft3(a0, a1, a2);
+    y[n2][0] = a0; y[n2][1] = a1; y[n2][2] = a2;
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 3; ++k1) {
+    cplx<T> z[5] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1], y[4][k1]};
+    dft5(z);
+#pragma unroll
+    for (int k2 = 0; k2 < 5; ++k2) x[(10 * k1 + 6 * k2) % 15] = z[k2];
+  }
+}
+
 // Last step of an 8-point DFT from the 4-point DFTs of the even (e) and odd
 // (o) inputs: X[j] = e_j + w8^j o_j, X[j+4] = e_j - w8^j o_j.  The 1/sqrt2 of
 // w8^1 = (1+i)/sqrt2 and w8^3 = (-1+i)/sqrt2 is applied inside the sums, each
@@ -260,12 +302,16 @@ FCAS_HD void dft(cplx<T>* x) {
     dft3(x[0], x[1], x[2]);
   } else if constexpr (R == 4) {
     dft4(x[0], x[1], x[2], x[3]);
+  } else if constexpr (R == 5) {
+    dft5(x);
   } else if constexpr (R == 8) {
     dft8(x);
+  } else if constexpr (R == 15) {
+    dft15(x);
   } else if constexpr (R == 16) {
     dft16(x);
   } else {
-    static_assert(R == 2 || R == 3 || R == 4 || R == 8 || R == 16, "unsupported radix");
+    static_assert(R == 2 || R == 3 || R == 4 || R == 5 || R == 8 || R == 15 || R == 16, "unsupported radix");
   }
 }
 

@@ -16,7 +16,8 @@
 //   k = k1 N2 + k2,  j = j1 + N1 j2,
 //   pass 1 (per column k2): B(j1, k2) = w_N^{k2 j1} sum_{k1} W(k1 N2 + k2) w_N1^{k1 j1}
 //   pass 2 (per row j1):    a(j1 + N1 j2) = sum_{k2} B(j1, k2) w_N2^{k2 j2}
-// with B stored row-major [series][j1][k2] in the workspace.
+// with B stored row-major [series][j1][k2] in the workspace.  Lengths too long
+// for two passes insert a middle pass (see Plan below).
 #pragma once
 
 #include <stdint.h>
@@ -35,7 +36,7 @@ struct SegDesc {
   int32_t k_lo, k_hi;   // inclusive in-band bins
   int32_t plan;         // FFT plan index
   int32_t registered;   // 1 once fcas_set_segment has completed
-  int32_t dk1;          // the plan's pass-1 register stride in bins (P1 N2)
+  int32_t dk1;          // the plan's pass-1 register stride in bins (P1 W1)
   int32_t reserved;
   double df;            // 1 / T
   double sigma[kMaxDet];
@@ -273,34 +274,72 @@ FCAS_HD void stage_gather(cplx<Real>* vs, const cplx<Real>* buf, int t) {
   for (int q = 0; q < E; ++q) vs[q] = buf[lds_pad<PAD>(t + q * P)];
 }
 
-// Compile-time description of a plan: N = N1 * N2.
+// Compile-time description of a plan.
+// Two-pass plans (NM = 1): N = N1 * N2,
 //   pass 1: C columns per work item, P1 = N1 / E1 threads per column
 //   pass 2: RW rows per work item,   P2 = N2 / E2 threads per row
-// LDS padding of the two passes' exchanges (see lds_pad): one spare element
-// in 16 for both (on gfx950 pass 1 runs 1.7x slower unpadded, pass 2 ~8%).
-constexpr int kPad1 = 4, kPad2 = 4;
+// Three-pass plans (NM > 1): N = N1 * NM * N2 with
+//   k = k1 NM N2 + km N2 + k2,  j = j1 + N1 jm + N1 NM j2,
+//   pass 1 (per column km N2 + k2 of its W1 = NM N2): the length-N1 transform over k1,
+//           stored as B1[j1][km N2 + k2]
+//   middle pass (per j1 and k2; CM adjacent k2 per work item, PM = NM / EM
+//           threads per transform): times w_N^{j1 (km N2 + k2)}, the
+//           length-NM transform over km, times w_{NM N2}^{jm k2}, stored in
+//           place as B2[j1][jm N2 + k2]
+//   pass 2 (per row j1 NM + jm, contiguous): the length-N2 transform over k2
+//           and the maximum of |a_0|^2 + |a_1|^2 over its samples
+// which is the four-step factorisation applied twice: both passes' row
+// segments stay contiguous, so every store and load moves whole 64-byte or
+// longer pieces even when N1 N2 exceeds what one work item can hold.
+// LDS padding of the exchanges (see lds_pad): one spare element in 16 for all
+// passes (on gfx950 pass 1 runs 1.7x slower unpadded, pass 2 ~8%).
+constexpr int kPad1 = 4, kPad2 = 4, kPadM = 4;
 
-template <int N1_, int E1_, class Rad1_, int C_, int N2_, int E2_, class Rad2_, int RW_>
+template <int N1_, int E1_, class Rad1_, int C_, int N2_, int E2_, class Rad2_, int RW_, int NM_ = 1, int EM_ = 1,
+          class RadM_ = Radices<1>, int CM_ = 1>
 struct Plan {
   static constexpr int N1 = N1_, E1 = E1_, C = C_, N2 = N2_, E2 = E2_, RW = RW_;
+  static constexpr int NM = NM_, EM = EM_, CM = CM_;
   using Rad1 = Rad1_;
   using Rad2 = Rad2_;
-  static constexpr int64_t N = (int64_t)N1 * N2;
-  static constexpr int P1 = N1 / E1, P2 = N2 / E2;
-  static constexpr int T1 = C * P1, T2 = RW * P2;           // threads per work item
-  static constexpr int TILES1 = N2 / C, TILES2 = N1 / RW;   // work items per evaluation
-  static constexpr int DK1 = P1 * N2;                       // bin stride between a pass-1 thread's registers
+  using RadM = RadM_;
+  static constexpr bool THREE = NM > 1;
+  static constexpr int W1 = NM * N2;                        // columns of pass 1 (its output row length)
+  static constexpr int ROWS2 = N1 * NM;                     // rows of pass 2
+  static constexpr int64_t N = (int64_t)N1 * NM * N2;
+  static constexpr int P1 = N1 / E1, P2 = N2 / E2, PM = NM / EM;
+  static constexpr int T1 = C * P1, T2 = RW * P2, TM = CM * PM;   // threads per work item
+  static constexpr int TILES1 = W1 / C, TILES2 = ROWS2 / RW;      // work items per evaluation
+  static constexpr int TILESM = THREE ? N1 * (N2 / CM) : 0;
+  static constexpr int DK1 = P1 * W1;                       // bin stride between a pass-1 thread's registers
   static constexpr int PARTS2 = TILES2 * (T2 / 64);         // pass-2 partials (one per wavefront)
   static_assert(Rad1::product() == N1, "pass-1 radices must multiply to N1");
   static_assert(Rad2::product() == N2, "pass-2 radices must multiply to N2");
-  static_assert(N1 % E1 == 0 && N2 % E2 == 0, "elements per thread must divide the length");
-  static_assert(N2 % C == 0 && N1 % RW == 0, "tiles must divide the transform");
+  static_assert(RadM::product() == NM, "middle-pass radices must multiply to NM");
+  static_assert(N1 % E1 == 0 && N2 % E2 == 0 && NM % EM == 0, "elements per thread must divide the length");
+  static_assert(W1 % C == 0 && ROWS2 % RW == 0 && N2 % CM == 0, "tiles must divide the transform");
   static_assert(T2 % 64 == 0 && (64 % P2 == 0 || P2 % 64 == 0), "pass-2 rows and wavefronts must nest");
+  // the middle pass works in place: at least one work-group barrier (between
+  // two stages) separates an item's loads from its stores
+  static_assert(!THREE || RadM::count >= 2, "the middle pass needs two or more stages");
+  static_assert(N < ((int64_t)1 << 30), "sample and bin indices are 32-bit");
 };
+
+// First output sample of pass-2 row `row`; the row's samples follow at a
+// stride of ROWS2.
+template <class PL>
+FCAS_HD int row_base(int row) {
+  if constexpr (PL::THREE) {
+    const int j1 = row / PL::NM;
+    return j1 + PL::N1 * (row - j1 * PL::NM);
+  } else {
+    return row;
+  }
+}
 
 // ---------------------------------------------------------------------------
 // Pass 1, thread (c, p) of column tile `tile`: prologue into registers.
-// Register q holds k1 = p + q P1, i.e. bin k = k1 N2 + k2.  Only positive
+// Register q holds k1 = p + q P1, i.e. bin k = k1 W1 + k2.  Only positive
 // frequencies are in band (k <= k_hi < N/2), so registers q >= E1/2
 // (k1 >= N1/2) are always zero and are left unset: the first stage reads
 // only the lower half.
@@ -309,7 +348,7 @@ struct Plan {
 // the delay ramps r_i(k) = exp(2 pi i k dly_i),
 //   W_m(k) = e_c(k) sum_i Q_im y^i_k r_i(k).
 // r_i is exact (FP64-reduced) at the thread's first bin and advanced by the
-// constant factor exp(2 pi i (P1 N2) dly_i) of the point's descriptor from
+// constant factor exp(2 pi i (P1 W1) dly_i) of the point's descriptor from
 // register to register.  Out-of-band registers read bin k_lo (any finite
 // value) and are cleared by a zero e_c, so no lane branches.
 // ---------------------------------------------------------------------------
@@ -330,7 +369,7 @@ FCAS_HD void pass1_fetch(Pass1Data<Real, PL, DT>& d, const SegDesc& sg, int tile
   constexpr int DK = PL::DK1;
   static_assert(DT > 0, "prefetch needs a compile-time detector count");
   const int k2 = tile * PL::C + c;
-  d.k0 = p * PL::N2 + k2;
+  d.k0 = p * PL::W1 + k2;
   const cplx<Real>* y = (const cplx<Real>*)sg.y;
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
@@ -400,7 +439,7 @@ FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, cons
   constexpr int DK = PL::DK1;
   const int n_det = DT > 0 ? DT : n_det_rt;
   const int k2 = tile * PL::C + c;
-  const int k0 = p * PL::N2 + k2;
+  const int k0 = p * PL::W1 + k2;
   const cplx<Real>* y = (const cplx<Real>*)sg.y;
   bool in[QH];
   int kk[QH];
@@ -435,22 +474,94 @@ FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, cons
 }
 
 // Pass 1 epilogue: store B[m][j1][k2] (the four-step twiddle is applied when
-// pass 2 loads the rows).
+// the next pass loads the rows).
 template <typename Real, class PL>
 FCAS_HD void pass1_store(cplx<Real> (&v)[2][PL::E1], cplx<Real>* slot, int tile, int c, int p) {
   const int k2 = tile * PL::C + c;
 #pragma unroll
   for (int q = 0; q < PL::E1; ++q) {
     const int j1 = p + q * PL::P1;
-    const int64_t o = (int64_t)j1 * PL::N2 + k2;
+    const int64_t o = (int64_t)j1 * PL::W1 + k2;
     stream_store(slot + o, v[0][q]);
     stream_store(slot + PL::N + o, v[1][q]);
   }
 }
 
-// Pass 2 prologue: thread (r, p) of row tile `tile` reads row j1 = tile RW + r,
-// register q holds k2 = p + q P2 (pass2_fetch), then multiplies by the
-// four-step twiddle w_N^{k2 j1} (pass2_twiddle).
+// ---------------------------------------------------------------------------
+// Middle pass of a three-pass plan, thread (c, p) of tile `tile`: the tile is
+// pass-1 row j1 = tile / (N2 / CM) and the CM adjacent columns k2 from
+// (tile mod (N2 / CM)) CM; register q holds km = p + q PM on input and
+// jm = p + q PM on output.
+// ---------------------------------------------------------------------------
+template <class PL>
+FCAS_HD void passm_coords(int tile, int c, int& j1, int& k2) {
+  constexpr int KT = PL::N2 / PL::CM;
+  j1 = tile / KT;
+  k2 = (tile - j1 * KT) * PL::CM + c;
+}
+
+template <typename Real, class PL>
+FCAS_HD void passm_fetch(cplx<Real> (&v)[2][PL::EM], const cplx<Real>* slot, int tile, int c, int p) {
+  int j1, k2;
+  passm_coords<PL>(tile, c, j1, k2);
+  const cplx<Real>* at = slot + (int64_t)j1 * PL::W1 + k2;
+#pragma unroll
+  for (int q = 0; q < PL::EM; ++q) {
+    const int o = (p + q * PL::PM) * PL::N2;
+    v[0][q] = stream_load(at + o);
+    v[1][q] = stream_load(at + PL::N + o);
+  }
+}
+
+// w_N^{j1 (km N2 + k2)} on input: exact at q = 0, then advanced by
+// w_N^{j1 PM N2} from register to register.
+template <typename Real, class PL>
+FCAS_HD void passm_twiddle_in(cplx<Real> (&v)[2][PL::EM], int tile, int c, int p) {
+  int j1, k2;
+  passm_coords<PL>(tile, c, j1, k2);
+  cplx<Real> t = twiddle<Real>(j1 * (p * PL::N2 + k2), (int)PL::N);     // < N1 W1 = N
+  const cplx<Real> st = twiddle<Real>(j1 * (PL::PM * PL::N2), (int)PL::N);
+#pragma unroll
+  for (int q = 0; q < PL::EM; ++q) {
+    v[0][q] = mul(v[0][q], t);
+    v[1][q] = mul(v[1][q], t);
+    if (q + 1 < PL::EM) t = mul(t, st);
+  }
+}
+
+// w_{NM N2}^{jm k2} on output: exact at q = 0, then advanced by w_{NM N2}^{PM k2}.
+template <typename Real, class PL>
+FCAS_HD void passm_twiddle_out(cplx<Real> (&v)[2][PL::EM], int tile, int c, int p) {
+  int j1, k2;
+  passm_coords<PL>(tile, c, j1, k2);
+  cplx<Real> t = twiddle<Real>(p * k2, PL::W1);                      // < PM N2 <= W1
+  const cplx<Real> st = twiddle<Real>(PL::PM * k2, PL::W1);
+#pragma unroll
+  for (int q = 0; q < PL::EM; ++q) {
+    v[0][q] = mul(v[0][q], t);
+    v[1][q] = mul(v[1][q], t);
+    if (q + 1 < PL::EM) t = mul(t, st);
+  }
+}
+
+// Store B2[m][j1][jm N2 + k2], over the elements the tile loaded.
+template <typename Real, class PL>
+FCAS_HD void passm_store(cplx<Real> (&v)[2][PL::EM], cplx<Real>* slot, int tile, int c, int p) {
+  int j1, k2;
+  passm_coords<PL>(tile, c, j1, k2);
+  cplx<Real>* at = slot + (int64_t)j1 * PL::W1 + k2;
+#pragma unroll
+  for (int q = 0; q < PL::EM; ++q) {
+    const int o = (p + q * PL::PM) * PL::N2;
+    stream_store(at + o, v[0][q]);
+    stream_store(at + PL::N + o, v[1][q]);
+  }
+}
+
+// Pass 2 prologue: thread (r, p) of row tile `tile` reads row tile RW + r,
+// register q holds k2 = p + q P2 (pass2_fetch); in a two-pass plan the row is
+// j1 and the four-step twiddle w_N^{k2 j1} follows (pass2_twiddle), in a
+// three-pass plan the middle pass has applied it.
 template <typename Real, class PL>
 FCAS_HD void pass2_fetch(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
   const int j1 = tile * PL::RW + r;
@@ -467,6 +578,7 @@ FCAS_HD void pass2_fetch(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int
 // advanced by the factor w_N^{P2 j1} from register to register.
 template <typename Real, class PL>
 FCAS_HD void pass2_twiddle(cplx<Real> (&v)[2][PL::E2], int tile, int r, int p) {
+  static_assert(!PL::THREE, "three-pass plans twiddle in the middle pass");
   const int j1 = tile * PL::RW + r;
   cplx<Real> t = twiddle<Real>(p * j1, (int)PL::N);                // p j1 < N
   const cplx<Real> st = twiddle<Real>(PL::P2 * j1, (int)PL::N);    // P2 j1 < N
@@ -481,16 +593,16 @@ FCAS_HD void pass2_twiddle(cplx<Real> (&v)[2][PL::E2], int tile, int r, int p) {
 template <typename Real, class PL>
 FCAS_HD void pass2_load(cplx<Real> (&v)[2][PL::E2], const cplx<Real>* slot, int tile, int r, int p) {
   pass2_fetch<Real, PL>(v, slot, tile, r, p);
-  pass2_twiddle<Real, PL>(v, tile, r, p);
+  if constexpr (!PL::THREE) pass2_twiddle<Real, PL>(v, tile, r, p);
 }
 
-// Pass 2 epilogue: Gamma^2_j = |a_0|^2 + |a_1|^2 at j = j1 + N1 (p + q P2),
+// Pass 2 epilogue: Gamma^2_j = |a_0|^2 + |a_1|^2 at j = row_base + ROWS2 (p + q P2),
 // for j_lo <= j < j_hi; the thread's largest value and, among equal values,
 // its smallest j (value -1 if none of its samples is in range).
 template <typename Real, class PL>
 FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p, Real& best, int& best_j,
                         int64_t j_lo = 0, int64_t j_hi = PL::N) {
-  const int j1 = tile * PL::RW + r;
+  const int j0 = row_base<PL>(tile * PL::RW + r);
   const int lo = j_lo > 0 ? (int)j_lo : 0;
   const int hi = j_hi < PL::N ? (int)j_hi : (int)PL::N;
   best = (Real)-1;
@@ -501,14 +613,14 @@ FCAS_HD void pass2_best(const cplx<Real> (&v)[2][PL::E2], int tile, int r, int p
       const Real g = norm2(v[0][q]) + norm2(v[1][q]);
       if (g > best) {   // j grows with q: ties keep the smaller j
         best = g;
-        best_j = j1 + PL::N1 * (p + q * PL::P2);
+        best_j = j0 + PL::ROWS2 * (p + q * PL::P2);
       }
     }
   } else {
 #pragma unroll
     for (int q = 0; q < PL::E2; ++q) {
       const Real g = norm2(v[0][q]) + norm2(v[1][q]);
-      const int j = j1 + PL::N1 * (p + q * PL::P2);
+      const int j = j0 + PL::ROWS2 * (p + q * PL::P2);
       if (g > best && j >= lo && j < hi) {
         best = g;
         best_j = j;

@@ -20,10 +20,45 @@ int fused_blocks_per_cu(int plan);
 
 // precision: 0 float, 1 double
 hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_passm(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);   // three-pass plans
 hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
-                           const int32_t* part_j, int n, const int32_t* plan_parts2, int32_t* counts,
-                           unsigned long long* evaluated, double* fitness, int32_t* argmax, hipStream_t s);
+                           const int32_t* part_j, int n, int part_stride, const int32_t* plan_parts2,
+                           int32_t* counts, unsigned long long* evaluated, double* fitness, int32_t* argmax,
+                           hipStream_t s);
+
+// Per-plan launch helpers of the per-precision translation units: the middle
+// pass exists only for three-pass plans, the fused kernel only for two-pass
+// ones; asked for the other kind they return hipErrorInvalidValue.
+template <typename Real, class PL>
+hipError_t launch_passm_plan(const PassArgs& a, int grid, hipStream_t s) {
+  if constexpr (PL::THREE) {
+    hipLaunchKernelGGL((k_passm<Real, PL>), dim3(grid), dim3(PL::TM), 0, s, a);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <class PL>
+hipError_t launch_fused_plan(const FusedArgs& f, int grid, hipStream_t s) {
+  if constexpr (!PL::THREE) {
+    hipLaunchKernelGGL((k_fused<float, PL>), dim3(grid), dim3(PL::T1), 0, s, f);
+    return hipGetLastError();
+  } else {
+    return hipErrorInvalidValue;
+  }
+}
+
+template <class PL>
+int fused_occupancy_plan() {
+  int nb = 0;
+  if constexpr (!PL::THREE) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_fused<float, PL>, PL::T1, 0) != hipSuccess)
+      nb = 0;
+  }
+  return nb;
+}
 
 // segment preparation: sigma_i^2 = 4 df sum_B f^-7/3 / S, y = 4 df x f^-7/6 / (S sigma), b = (f/f*)^-1/3
 hipError_t launch_segment_sigma(const double* psd, int n_det, int64_t half, int k_lo, int k_hi, double df,

@@ -88,6 +88,25 @@ static void run(const SegDesc& sg, const EvalDesc& ev, int n_det, std::vector<do
         regs, bufs, tw1, [](size_t t) { return (int)(t % PL::C); }, [](size_t t) { return (int)(t / PL::C); });
     for (int tid = 0; tid < PL::T1; ++tid) pass1_store<Real, PL>(regs[tid].v, ws.data(), tile, tid % PL::C, tid / PL::C);
   }
+  if constexpr (PL::THREE) {
+    std::vector<cplx<Real>> twm(PL::NM);
+    for (int m = 0; m < PL::NM; ++m) twm[m] = twiddle<Real>(m, PL::NM);
+    const int LPM = lds_padded_len<kPadM>(PL::NM);
+    for (int tile = 0; tile < PL::N1 * (PL::N2 / PL::CM); ++tile) {
+      std::vector<Regs<Real, PL::EM>> regs(PL::TM);
+      std::vector<std::vector<cplx<Real>>> bufs(PL::CM, std::vector<cplx<Real>>(LPM));
+      for (int tid = 0; tid < PL::TM; ++tid) {
+        passm_fetch<Real, PL>(regs[tid].v, ws.data(), tile, tid % PL::CM, tid / PL::CM);
+        passm_twiddle_in<Real, PL>(regs[tid].v, tile, tid % PL::CM, tid / PL::CM);
+      }
+      emu_stages<Real, PL::NM, PL::EM, typename PL::RadM, 0, 1, false, kPadM>(
+          regs, bufs, twm, [](size_t t) { return (int)(t % PL::CM); }, [](size_t t) { return (int)(t / PL::CM); });
+      for (int tid = 0; tid < PL::TM; ++tid) {
+        passm_twiddle_out<Real, PL>(regs[tid].v, tile, tid % PL::CM, tid / PL::CM);
+        passm_store<Real, PL>(regs[tid].v, ws.data(), tile, tid % PL::CM, tid / PL::CM);
+      }
+    }
+  }
   series.assign(N, -1.0);
   bg = -1;
   bj = 0x7fffffff;
@@ -100,9 +119,9 @@ static void run(const SegDesc& sg, const EvalDesc& ev, int n_det, std::vector<do
         regs, bufs, tw2, [](size_t t) { return (int)(t / PL::P2); }, [](size_t t) { return (int)(t % PL::P2); });
     for (int tid = 0; tid < PL::T2; ++tid) {
       const int r = tid / PL::P2, p = tid % PL::P2;
-      const int j1 = tile * PL::RW + r;
+      const int j0 = row_base<PL>(tile * PL::RW + r);
       for (int q = 0; q < PL::E2; ++q) {
-        const int64_t j = j1 + (int64_t)PL::N1 * (p + q * PL::P2);
+        const int64_t j = j0 + (int64_t)PL::ROWS2 * (p + q * PL::P2);
         if (series.at(j) != -1.0) { std::fprintf(stderr, "sample %lld written twice\n", (long long)j); std::exit(4); }
         series.at(j) = (double)(norm2(regs[tid].v[0][q]) + norm2(regs[tid].v[1][q]));
       }
