@@ -60,14 +60,16 @@ constexpr bool kJointExchange = sizeof(Real) == 4;
 template <typename Real>
 constexpr int kLdsSeries = kJointExchange<Real> ? 2 : 1;
 
-// All stages of both series of one transform.
-template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF, bool WAVE, int PAD>
+// All stages of both series of one transform; JOINT: both series exchange
+// through LDS together (buf0, buf1), else they take turns in buf0.
+template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF, bool WAVE, int PAD,
+          bool JOINT = kJointExchange<Real>>
 __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf0, cplx<Real>* buf1,
                                            const cplx<Real>* tw, int t) {
   if constexpr (I < Rad::count) {
     constexpr int R = Rad::value[I];
     constexpr bool LAST = (I == Rad::count - 1);
-    if constexpr (kJointExchange<Real>) {
+    if constexpr (JOINT) {
       stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[0], buf0, tw, t);
       stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[1], buf1, tw, t);
       if constexpr (!LAST) {
@@ -87,16 +89,37 @@ __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* bu
         }
       }
     }
-    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE, PAD>(v, buf0, buf1, tw, t);
+    run_stages<Real, PL, L, E, Rad, I + 1, Ns * R, false, WAVE, PAD, JOINT>(v, buf0, buf1, tw, t);
+  }
+}
+
+// Pass-1 work item -> (list position in the launch, column tile).  Point-major
+// (every tile of one point, then the next point) for two-pass plans, whose
+// segment data stay in the L2 anyway; tile-major for the long three-pass
+// segments (112 MB of data at one hour), so that the work-groups in flight
+// take one tile of many points and share its data in the cache instead of
+// each point re-reading the whole segment from HBM.
+template <class PL>
+constexpr bool kTileMajor1 = PL::THREE;
+
+template <class PL>
+__device__ __forceinline__ void pass1_decode(int item, int span, int& slot, int& tile) {
+  if constexpr (kTileMajor1<PL>) {
+    tile = item / span;
+    slot = item - tile * span;
+  } else {
+    slot = item / PL::TILES1;
+    tile = item - slot * PL::TILES1;
   }
 }
 
 template <typename Real, class PL, int DT>
-__device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, const PassArgs& a, int item, int c,
-                                                 int p) {
-  const int slot = item / PL::TILES1;
+__device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, const PassArgs& a, int item, int span,
+                                                 int c, int p) {
+  int slot, tile;
+  pass1_decode<PL>(item, span, slot, tile);
   const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
-  pass1_fetch<Real, PL, DT>(d, a.segs[ev.seg], item - slot * PL::TILES1, c, p);
+  pass1_fetch<Real, PL, DT>(d, a.segs[ev.seg], tile, c, p);
 }
 
 // LDS exchange buffers of the two passes: padded length of one transform and
@@ -114,7 +137,8 @@ __device__ __forceinline__ void pass1_body(const PassArgs& a, cplx<Real>* lds, c
                                            int nblocks) {
   constexpr int LP = PassLds<Real, PL>::LP1;
   const int tid = threadIdx.x;
-  const int items = launch_span(a) * PL::TILES1;
+  const int span = launch_span(a);
+  const int items = span * PL::TILES1;
   const int c = tid % PL::C, p = tid / PL::C;
   cplx<Real>* buf0 = lds + c * LP;
   cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::C + c) * LP : buf0;
@@ -124,21 +148,21 @@ __device__ __forceinline__ void pass1_body(const PassArgs& a, cplx<Real>* lds, c
     // of prefetch registers)
     Pass1Data<Real, PL, DT> d;
     int item = block;
-    if (item < items) pass1_fetch_item<Real, PL, DT>(d, a, item, c, p);
+    if (item < items) pass1_fetch_item<Real, PL, DT>(d, a, item, span, c, p);
     for (; item < items; item += nblocks) {
-      const int slot = item / PL::TILES1;
-      const int tile = item - slot * PL::TILES1;
+      int slot, tile;
+      pass1_decode<PL>(item, span, slot, tile);
       cplx<Real> v[2][PL::E1];
       pass1_compute<Real, PL, DT>(v, d, a.evals[a.list[a.chunk_begin + slot]]);
       const int next = item + nblocks;
-      if (next < items) pass1_fetch_item<Real, PL, DT>(d, a, next, c, p);
+      if (next < items) pass1_fetch_item<Real, PL, DT>(d, a, next, span, c, p);
       run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, false, kPad1>(v, buf0, buf1, tw, p);
       pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
     }
   } else {
     for (int item = block; item < items; item += nblocks) {
-      const int slot = item / PL::TILES1;
-      const int tile = item - slot * PL::TILES1;
+      int slot, tile;
+      pass1_decode<PL>(item, span, slot, tile);
       const int e = a.list[a.chunk_begin + slot];
       const EvalDesc& ev = a.evals[e];
       const SegDesc& sg = a.segs[ev.seg];
@@ -171,6 +195,15 @@ __global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))
 // one pass-1 row, so every load and store instruction moves CM * 8 bytes of
 // contiguous row per transform element (128 bytes at CM = 16).
 // ---------------------------------------------------------------------------
+// Exchange mode and software prefetch of the middle pass.  Measured on the
+// hour-long plans: the series taking turns in LDS (half the LDS, so 5 instead
+// of 2 work-groups per CU) runs 1.75x faster than both at once, and a second
+// register set for prefetching then gains nothing, so neither is used.
+constexpr bool kPassmJoint = false;
+constexpr bool kPassmPrefetch = false;
+template <typename Real>
+constexpr bool kPassmJointFor = kPassmJoint && kJointExchange<Real>;
+
 template <typename Real, class PL>
 __device__ __forceinline__ void passm_fetch_item(cplx<Real> (&v)[2][PL::EM], const PassArgs& a, int item, int c,
                                                  int p) {
@@ -184,15 +217,16 @@ __device__ __forceinline__ void passm_item(cplx<Real> (&v)[2][PL::EM], const Pas
   const int slot = item / PL::TILESM;
   const int tile = item - slot * PL::TILESM;
   passm_twiddle_in<Real, PL>(v, tile, c, p);
-  run_stages<Real, PL, PL::NM, PL::EM, typename PL::RadM, 0, 1, false, false, kPadM>(v, buf0, buf1, tw, p);
+  run_stages<Real, PL, PL::NM, PL::EM, typename PL::RadM, 0, 1, false, false, kPadM, kPassmJointFor<Real>>(
+      v, buf0, buf1, tw, p);
   passm_twiddle_out<Real, PL>(v, tile, c, p);
   passm_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
 }
 
-// Middle pass on the items of `a` taken by work-group `block` of `nblocks`,
-// with the next item's loads in flight while one is transformed (two register
-// sets).  Items cover disjoint workspace elements, so a prefetch never reads
-// what another item stores.
+// Middle pass on the items of `a` taken by work-group `block` of `nblocks`;
+// with kPassmPrefetch the next item's loads are in flight while one is
+// transformed (two register sets).  Items cover disjoint workspace elements,
+// so a prefetch never reads what another item stores.
 template <typename Real, class PL>
 __device__ __forceinline__ void passm_body(const PassArgs& a, cplx<Real>* lds, const cplx<Real>* tw, int block,
                                            int nblocks) {
@@ -201,25 +235,33 @@ __device__ __forceinline__ void passm_body(const PassArgs& a, cplx<Real>* lds, c
   const int items = launch_span(a) * PL::TILESM;
   const int c = tid % PL::CM, p = tid / PL::CM;
   cplx<Real>* buf0 = lds + c * LP;
-  cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::CM + c) * LP : buf0;
-  cplx<Real> va[2][PL::EM], vb[2][PL::EM];
-  int item = block;
-  if (item < items) passm_fetch_item<Real, PL>(va, a, item, c, p);
-  while (item < items) {
-    const int next = item + nblocks;
-    if (next < items) passm_fetch_item<Real, PL>(vb, a, next, c, p);
-    passm_item<Real, PL>(va, a, item, buf0, buf1, tw, c, p);
-    if (next >= items) break;
-    item = next + nblocks;
+  cplx<Real>* buf1 = kPassmJointFor<Real> ? lds + (PL::CM + c) * LP : buf0;
+  if constexpr (kPassmPrefetch) {
+    cplx<Real> va[2][PL::EM], vb[2][PL::EM];
+    int item = block;
     if (item < items) passm_fetch_item<Real, PL>(va, a, item, c, p);
-    passm_item<Real, PL>(vb, a, next, buf0, buf1, tw, c, p);
+    while (item < items) {
+      const int next = item + nblocks;
+      if (next < items) passm_fetch_item<Real, PL>(vb, a, next, c, p);
+      passm_item<Real, PL>(va, a, item, buf0, buf1, tw, c, p);
+      if (next >= items) break;
+      item = next + nblocks;
+      if (item < items) passm_fetch_item<Real, PL>(va, a, item, c, p);
+      passm_item<Real, PL>(vb, a, next, buf0, buf1, tw, c, p);
+    }
+  } else {
+    for (int item = block; item < items; item += nblocks) {
+      cplx<Real> v[2][PL::EM];
+      passm_fetch_item<Real, PL>(v, a, item, c, p);
+      passm_item<Real, PL>(v, a, item, buf0, buf1, tw, c, p);
+    }
   }
 }
 
 template <typename Real, class PL>
 __global__ void __launch_bounds__(PL::TM) k_passm(PassArgs a) {
   static_assert(PL::THREE, "two-pass plans have no middle pass");
-  __shared__ cplx<Real> lds[kLdsSeries<Real> * PL::CM * lds_padded_len<kPadM>(PL::NM)];
+  __shared__ cplx<Real> lds[(kPassmJointFor<Real> ? 2 : 1) * PL::CM * lds_padded_len<kPadM>(PL::NM)];
   __shared__ cplx<Real> tw[PL::NM];
   init_twiddles<Real, PL::NM, PL::TM>(tw);
   passm_body<Real, PL>(a, lds, tw, blockIdx.x, gridDim.x);

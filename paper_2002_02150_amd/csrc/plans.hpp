@@ -16,7 +16,7 @@ namespace fcas {
 // TILES2 * T2 / 64 per evaluation, at most kMaxParts2 over all plans.  A
 // context sizes its partial buffers by the largest count among the plans its
 // maximum segment length admits.
-constexpr int kMaxParts2 = 8192;
+constexpr int kMaxParts2 = 16384;
 
 template <int... R>
 using Rad = Radices<R...>;
@@ -50,10 +50,13 @@ using Rad = Radices<R...>;
   X(22,  65536,   256, 8, (8, 8, 4),    8, 8,    256, 8, (8, 8, 4),       8, 8, 1, 1, (1), 1, 1) \
   X(23,  65536,   128, 8, (8, 4, 4),    16, 16,  512, 8, (8, 8, 8),       4, 4, 1, 1, (1), 1, 1) \
   X(24, 131072,   128, 8, (8, 4, 4),    16, 16, 1024, 8, (8, 8, 8, 2),    2, 2, 1, 1, (1), 1, 1) \
-  /* three passes (N = N1 * 225 * N2): 225 s, 30 min and one hour at 2048 Hz */                    \
+  /* three passes (N = N1 * 225 * N2): 225 s, 30 min and one hour at 2048 Hz;  */                 \
+  /* 32 pass-1 columns per work item make 256-byte store segments              */                 \
   X(25,  460800,   32, 8, (8, 4),       64, 64,   64, 8, (8, 8),          32, 32, 225, 15, (15, 15), 16, 8) \
-  X(26, 3686400,  256, 8, (8, 8, 4),    8, 8,     64, 8, (8, 8),          32, 32, 225, 15, (15, 15), 16, 8) \
-  X(27, 7372800,  256, 8, (8, 8, 4),    8, 8,    128, 16, (16, 8),        32, 16, 225, 15, (15, 15), 16, 8)
+  X(26, 3686400,   64, 8, (8, 8),       32, 32,  256, 8, (8, 8, 4),       8, 8, 225, 15, (15, 15), 16, 8) \
+  X(27, 7372800,   64, 8, (8, 8),       32, 32,  512, 8, (8, 8, 8),       4, 4, 225, 15, (15, 15), 16, 8) \
+  X(28, 7372800,  128, 8, (8, 4, 4),    16, 16,  256, 8, (8, 8, 4),       8, 8, 225, 15, (15, 15), 16, 8) \
+  X(29, 3686400,  256, 8, (8, 8, 4),    8, 8,     64, 8, (8, 8),          32, 32, 225, 15, (15, 15), 16, 8)
 // clang-format on
 
 #define FCAS_UNPAREN(...) __VA_ARGS__
@@ -68,7 +71,7 @@ using Rad = Radices<R...>;
 
 FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
 
-constexpr int kNumPlans = 28;
+constexpr int kNumPlans = 30;
 
 struct PlanInfo {
   int64_t n;

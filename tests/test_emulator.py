@@ -21,7 +21,7 @@ BIN = os.path.join(ROOT, "tests", "emu", "_build", "fcas_emu")
 PLANS = {0: 2048, 1: 4096, 2: 8192, 3: 16384, 4: 32768, 5: 65536, 6: 131072, 7: 262144,
          8: 24576, 9: 49152, 10: 98304, 11: 196608,
          12: 131072, 13: 131072, 14: 131072, 15: 131072, 16: 262144, 17: 65536, 18: 196608, 19: 8192,
-         20: 262144, 21: 196608, 22: 65536, 23: 65536, 24: 131072, 25: 460800, 26: 3686400, 27: 7372800}
+         20: 262144, 21: 196608, 22: 65536, 23: 65536, 24: 131072, 25: 460800, 26: 3686400, 27: 7372800, 28: 7372800, 29: 3686400}
 
 
 @pytest.fixture(scope="module")
@@ -59,7 +59,7 @@ def _run(emu, tmp_path, case, theta, plan, prec):
     (12, "HLVK", 0), (13, "HLVK", 0), (14, "HLVK", 0), (15, "HLVK", 0), (16, "HLVK", 0), (17, "HLV", 0),
     (18, "HLVK", 0), (19, "HL", 0), (12, "HLVK", 1), (18, "HL", 1), (20, "HLVK", 0), (20, "HL", 1),
     (21, "HLVK", 0), (22, "HLV", 0), (23, "HLVK", 0), (24, "HLVK", 0), (21, "HL", 1), (24, "HL", 1),
-    (25, "HLVK", 0), (25, "HL", 1), (27, "HLVK", 0),
+    (25, "HLVK", 0), (25, "HL", 1), (27, "HLVK", 0), (29, "HL", 1),
 ])
 def test_emulated_path_matches_oracle(emu, tmp_path, plan, names, prec):
     n = PLANS[plan]
