@@ -45,10 +45,14 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1280,
                     help="points the oracle evaluates for cpu_baseline (the first 320 also for parity)")
     ap.add_argument("--schedule", choices=("fused", "two-pass"), default="two-pass")
-    ap.add_argument("--config", choices=("search", "batched", "gradient", "sweep"), default="search",
+    ap.add_argument("--config", choices=("search", "batched", "gradient", "sweep", "hour"), default="search",
                     help="search: the benchmark configuration (default); batched: 256 ragged segments, "
                          "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source; "
-                         "sweep: fitness batches of 320 to 20480 points")
+                         "sweep: fitness batches of 320 to 20480 points; hour: the PSO search of one hour-long "
+                         "segment (7,372,800 samples per detector, three-pass FFT)")
+    ap.add_argument("--hour-workspace-gib", type=float, default=0.0,
+                    help="hour: FFT workspace in GiB (0: the library default, 8 GiB = 72 points, five launches per "
+                         "pass for 320 points; measured faster than one 37.7 GB workspace for the whole batch)")
     ap.add_argument("--launch-counts", action="store_true",
                     help="record the points evaluated by each eager launch (adds a sync per step)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -147,13 +151,13 @@ POLISH_STEPS = 10
 GRAPH_GROUP = 20   # PSO iterations per replayed HIP graph
 
 
-def fp64_plain_rate(torch, net, xf, psd_d, thetas, dev):
+def fp64_plain_rate(torch, net, xf, psd_d, thetas, dev, n_samples=N_SAMPLES):
     """Per-particle FP64 path: the same kernels in double precision, one
     evaluation per call, no batching."""
     import synth
     from paper_2002_02150_amd import FP64, Context
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=synth.SEARCH_BOX_30HZ_LO,
-                               box_hi=synth.SEARCH_BOX_30HZ_HI, precision=FP64, max_batch=1, max_samples=N_SAMPLES)
+                               box_hi=synth.SEARCH_BOX_30HZ_HI, precision=FP64, max_batch=1, max_samples=n_samples)
     ctx.set_segment(0, xf, psd_d)
     seg = torch.zeros(1, dtype=torch.int32, device=dev)
     rows = [thetas[i:i + 1].contiguous() for i in range(thetas.shape[0])]
@@ -186,7 +190,7 @@ def _oracle_ready(_):
     return True
 
 
-def cpu_baseline(xf_np, psd, net, thetas, sample):
+def cpu_baseline(xf_np, psd, net, thetas, sample, shape="4 det x 131072 samples"):
     """The FP64 oracle on the host cores: a pool of one process per core (the
     segment handed over once, the pool started before timing) evaluates
     `sample` points uniform in the rectangle (the first PSO batch, then more
@@ -211,7 +215,7 @@ def cpu_baseline(xf_np, psd, net, thetas, sample):
         ref[i::cores] = part
     return dict(value=len(th) / dt, unit="evals/s", cores=cores, kind="oracle",
                 sample=f"{len(th)} fitness evaluations uniform in the rectangle (the first PSO batch and more "
-                       f"drawn alike; 4 det x 131072 samples), one single-threaded process per host core, {dt:.1f} s wall"), \
+                       f"drawn alike; {shape}), one single-threaded process per host core, {dt:.1f} s wall"), \
         seg, ref[:len(thetas)]
 
 
@@ -409,6 +413,129 @@ def run_sweep(a, torch, dev):
     print(json.dumps(out))
 
 
+HOUR_SAMPLES = 7372800
+PAPER_KNL_HOUR = 40 * 1000 / (54.9 * 60)   # one PSO run (40 particles, 1000 iterations) in 54.9 min on KNL
+
+
+def pass_roofline(name, avg_ms, alg_bytes):
+    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg_bytes}
+
+
+def run_hour(a, torch, dev):
+    """The paper's own layout (Sec. IV): one hour-long segment of 4-detector data
+    at 2048 Hz (7,372,800 samples per detector, three-pass FFT plan) with an
+    SNR-10 injection; PSO 8 runs x 40 particles, one step = the fitness of the
+    320 particles and the swarm update, captured as HIP graphs of 20 steps; the
+    timed region ends with the best of the runs and its gradient polish."""
+    import synth
+    from paper_2002_02150_amd import Context, PsoConfig, Swarm
+    from paper_2002_02150_amd.params import chirp_times
+    N, n = HOUR_SAMPLES, RUNS * PARTICLES
+    net = synth.network("HLVK")
+    psd = synth.psd_matrix(4, N, FS)
+    noise = synth.noise_matrix(5, 0, psd, N, FS)
+    inj = synth.draw_injection(np.random.default_rng(synth.seed_sequence(5, 0, 1000)), N)
+    t0, t15 = chirp_times(inj["m1"], inj["m2"], F_LOW)
+    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    ws = int(a.hour_workspace_gib * (1 << 30))
+    ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
+                               max_samples=N, workspace_bytes=ws, schedule=SCHEDULES[a.schedule])
+    xf = torch.from_numpy(noise).to(dev)
+    psd_d = torch.from_numpy(np.ascontiguousarray(psd)).to(dev)
+    ctx.inject(xf, psd_d, inj["alpha"], inj["delta"], t0, t15, inj["psi"], inj["phi_c"], inj["cos_iota"],
+               inj["tc_sample"] / FS, 10.0)
+    ctx.set_segment(0, xf, psd_d)
+    sw = Swarm(ctx, PsoConfig(n_runs=RUNS, n_particles=PARTICLES, n_iter=1000, seed=20020215))
+    first_batch = sw.init().clone()
+    search = Search(torch, ctx, sw)
+    for _ in range(a.warmup):
+        search.iteration()
+    search.capture(GRAPH_GROUP)
+    torch.cuda.synchronize()
+    ev0 = ctx.evaluated()
+    t = time.perf_counter()
+    search.run(a.steps)
+    ev_mid = ctx.evaluated()
+    search.polish()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    # eager steps with HIP events around the three FFT passes
+    eager = min(a.steps, 20)
+    ev2 = ctx.evaluated()
+    for _ in range(eager):
+        search.iteration(timed=True)
+    torch.cuda.synchronize()
+    ev3 = ctx.evaluated()
+    timing = {k: ctx.read_timing(k) for k in ("pass1", "passm", "pass2")}
+    pts = ev3 - ev2
+    K = int(1000.0 * N / FS) - int(30.0 * N / FS)   # in-band bins 30 < f <= 1000 Hz
+    per_point = {"pass1": 16 * N, "passm": 32 * N, "pass2": 16 * N}
+    kname = {"pass1": "k_pass1", "passm": "k_passm", "pass2": "k_pass2"}
+    lines = {}
+    for k, (ms, cnt) in timing.items():
+        alg = pts / max(cnt, 1) * per_point[k] + (8 * K * 4 + 8 * K if k == "pass1" else 0)
+        lines[k] = pass_roofline(kname[k], ms / max(cnt, 1), alg)
+        lines[k]["ms_per_step"] = ms / eager
+    dom = max(lines, key=lambda k: lines[k]["ms_per_step"])
+    # measured HBM bytes per point of each pass (rocprofv3 FETCH_SIZE / WRITE_SIZE
+    # runs of this configuration, calibrated on a device copy), valid only for
+    # the kernel sources they were taken on
+    tf = os.path.join(ROOT, "profiles", "traffic_hour.json")
+    if os.path.exists(tf):
+        tr = json.load(open(tf))
+        if tr.get("kernel_hash") == kernel_hash():
+            for k in lines:
+                bpp = tr.get("kernels", {}).get(kname[k], {}).get("bytes_per_point")
+                if bpp is not None:
+                    lines[k]["traffic"] = bpp * pts / max(timing[k][1], 1)
+    value = (ev_mid - ev0) / dt
+    out = {
+        "metric": "coherent-fitness evals/s, 4 det x 7,372,800 samples (one hour at 2048 Hz)",
+        "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64phase", "data": "synthetic",
+        "config": {"workload": "4 detectors (HLVK), one 60-min segment at 2048 Hz (7,372,800 samples), SNR-10 SPA "
+                               "injection; PSO 8 runs x 40 particles, one step = fitness of the 320 particles + "
+                               "swarm update (captured HIP graphs of 20 steps); the timed region ends with the best "
+                               f"of the runs and a {POLISH_STEPS}-step gradient polish of that point",
+                   "global_batch": n, "seq_len": N, "parallelism": "single-gpu",
+                   "workspace_bytes": ctx.workspace_bytes},
+        "roofline": dict(lines[dom], traffic=lines[dom].get("traffic")),
+        "passes": lines,
+        "paper_context": {"value": PAPER_KNL_HOUR, "unit": "evals/s",
+                          "what": "one PSO run (40 particles, 1000 iterations) on 60 min of data took 54.9 min "
+                                  "(median) on one KNL node; other hardware, shown for context"},
+        "kernel_hash": kernel_hash(),
+        "points_per_s": a.steps * n / dt, "evaluated_fraction": (ev_mid - ev0) / (a.steps * n),
+        "best": {"fitness": search.pol_f.item(), "argmax": search.pol_j.item()},
+    }
+    if not a.no_fp64:
+        rate64 = fp64_plain_rate(torch, net, xf, psd_d, first_batch[:8].contiguous(), dev, n_samples=N)
+        out["fp64_plain"] = {"value": rate64, "unit": "evals/s", "speedup": value / rate64,
+                             "what": "same kernels in FP64, one evaluation per call, no graph"}
+    if not a.no_cpu_baseline:
+        sample = first_batch[:32].cpu().numpy()
+        out["cpu_baseline"], oseg, ref = cpu_baseline(xf.cpu().numpy(), psd_d.cpu().numpy(), net, sample, 32,
+                                                      shape="4 det x 7,372,800 samples")
+        out["parity"] = parity(torch, ctx, oseg, net, sample, ref, dev)
+    out["evaluated_total"] = ctx.evaluated()   # every point the float passes processed in this process
+    ctx.close()
+    calib_copy(a, torch, dev, out)
+    print(json.dumps(out))
+
+
+def calib_copy(a, torch, dev, out):
+    """One device-to-device copy of --calib-copy-mib MiB (HBM counter calibration)."""
+    if a.calib_copy_mib:
+        src = torch.ones(a.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = src.numel() * 4
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -421,13 +548,15 @@ def main():
     from paper_2002_02150_amd import PsoConfig, Swarm
     dev = torch.device("cuda", 0)
     if a.steps is None:
-        a.steps = {"search": 2000, "batched": 20, "gradient": 50, "sweep": 20}[a.config]
+        a.steps = {"search": 2000, "batched": 20, "gradient": 50, "sweep": 20, "hour": 200}[a.config]
     if a.config == "batched":
         return run_batched(a, torch, dev)
     if a.config == "gradient":
         return run_gradient(a, torch, dev)
     if a.config == "sweep":
         return run_sweep(a, torch, dev)
+    if a.config == "hour":
+        return run_hour(a, torch, dev)
     ctx, net, xf, psd_d, inj = make_workload(torch, dev, a.schedule)
     sw = Swarm(ctx, PsoConfig(n_runs=RUNS, n_particles=PARTICLES, n_iter=2000, seed=20020215))
     first_batch = sw.init().clone()
@@ -537,12 +666,7 @@ def main():
     ctx.close()
     if per_launch:
         out["eager_launch_points"] = per_launch
-    if a.calib_copy_mib:
-        src = torch.ones(a.calib_copy_mib << 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["calib_copy_bytes"] = src.numel() * 4
+    calib_copy(a, torch, dev, out)
     print(json.dumps(out))
 
 

@@ -168,6 +168,19 @@ def test_full_search_small():
         assert d["rho0_sq"] > 0
 
 
+def test_single_segment_search_small():
+    """The paper's layout (the whole stretch one segment, three-pass FFT plan,
+    one injection, batched runs, polish) end to end on a 225-s stretch."""
+    require_gpu()
+    from paper_2002_02150_amd.full_search import run_single_segment
+    out = run_single_segment(minutes=3.75, iters=40, runs=2, polish_steps=3, log=lambda s: None)
+    assert out["samples"] == 460800 and out["points_per_iteration"] == 80
+    assert out["evaluated_points"] > 0 and out["t_run_s"] > 0
+    d = out["injection"]
+    assert d["rho_sq"] >= d["rho_sq_pso"] - 1e-9 and d["rho0_sq"] > 0
+    assert abs(d["rho0_sq"] / d["snr"] ** 2 - 1.0) < 0.5
+
+
 def test_detection_study_small():
     """The detection-statistics study (time-slid noise-only segments, injected
     segments, one batched search, lognormal threshold, detection probability
