@@ -102,6 +102,30 @@ def psd_analytic(f, s0: float = 1.0):
     return out
 
 
+# Per-detector stand-ins for the detector noise curves (which are not
+# available here): the analytic curve with its knee moved and its level
+# scaled, and narrow spectral lines (mains harmonics, suspension
+# resonances) on some detectors.  Row i uses entry i mod 4.
+NETWORK_KNEES = (215.0, 170.0, 260.0, 300.0)
+NETWORK_SCALES = (1.0, 2.2, 0.6, 3.5)
+NETWORK_LINES = (((60.0, 2.0, 40.0), (120.0, 2.0, 10.0)), ((500.0, 3.0, 300.0),), (), ((50.0, 1.5, 80.0),))
+
+
+def psd_network(n_det: int, n_samples: int, fs: float):
+    """(D, N/2+1) float64 PSD rows that differ between detectors (knee, level
+    and lines; see NETWORK_*): each detector gets its own sigma_i and
+    over-whitening."""
+    f = np.arange(n_samples // 2 + 1) * (fs / n_samples)
+    rows = []
+    for i in range(n_det):
+        k = i % 4
+        row = psd_analytic(f * (215.0 / NETWORK_KNEES[k]), NETWORK_SCALES[k])
+        for f_line, width, height in NETWORK_LINES[k]:
+            row = row * (1.0 + height * np.exp(-0.5 * ((f - f_line) / width) ** 2))
+        rows.append(row)
+    return np.stack(rows)
+
+
 def psd_matrix(n_det: int, n_samples: int, fs: float, s0: float = 1.0):
     """(D, N/2+1) float64 PSD rows, one per detector (all the same curve)."""
     f = np.arange(n_samples // 2 + 1) * (fs / n_samples)

@@ -13,11 +13,13 @@ from oracle import signal as S
 
 class Case:
     def __init__(self, names, n_samples, fs, f_low=30.0, f_high=1000.0, snr=None, noise=True,
-                 cfg=0, realization=0, inj_seed=None, s0=1.0):
+                 cfg=0, realization=0, inj_seed=None, s0=1.0, psd="same"):
         self.net = synth.network(names)
         self.n_samples, self.fs, self.f_low, self.f_high = n_samples, fs, f_low, f_high
         D = self.net.n_det
-        self.psd = synth.psd_matrix(D, n_samples, fs, s0)
+        # "same": one analytic curve for every detector; "network": a distinct
+        # curve per detector (synth.psd_network)
+        self.psd = synth.psd_matrix(D, n_samples, fs, s0) if psd == "same" else synth.psd_network(D, n_samples, fs)
         xf = np.zeros((D, n_samples // 2 + 1), dtype=np.complex128)
         if noise:
             xf += synth.noise_matrix(cfg, realization, self.psd, n_samples, fs)

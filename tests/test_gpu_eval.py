@@ -73,6 +73,33 @@ def test_noiseless_identity_on_gpu(prec, tol):
     ctx.close()
 
 
+@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
+def test_detector_specific_noise_curves(prec):
+    """Every detector with its own noise curve (knee, level, spectral lines:
+    its own sigma_i and over-whitening): parity with the oracle on a batch with
+    near, uniform, corner and outside points, and the noiseless identity
+    Gamma^2(theta_0) = SNR^2 on the injected sample."""
+    require_gpu()
+    case = Case("HLVK", 16384, 2048.0, snr=12.0, cfg=16, psd="network")
+    rng = np.random.default_rng(160 + prec)
+    th = thetas_for(case, rng)
+    ctx = make_ctx(case, prec, max_batch=len(th))
+    upload(ctx, 0, case)
+    f, j = ctx.eval(torch.from_numpy(th).to(dev()), torch.zeros(len(th), dtype=torch.int32, device=dev()))
+    f, j = f.cpu().numpy(), j.cpu().numpy()
+    fo, jo = oracle_eval(case, th)
+    assert_parity(case, th, f, j, fo, jo, 1e-4 if prec == 0 else 1e-9)
+    ctx.close()
+    clean = Case("HLV", 16384, 2048.0, snr=11.0, noise=False, cfg=17, psd="network")
+    ctx = make_ctx(clean, prec, max_batch=1)
+    upload(ctx, 0, clean)
+    f, j = ctx.eval(torch.from_numpy(clean.theta0[None, :].copy()).to(dev()),
+                    torch.zeros(1, dtype=torch.int32, device=dev()))
+    assert f.item() == pytest.approx(121.0, rel=1e-4 if prec == 0 else 1e-10)
+    assert j.item() == clean.inj["tc_sample"]
+    ctx.close()
+
+
 def test_ragged_segments_in_one_call():
     """Segments of different lengths (different FFT plans) interleaved in one batch."""
     require_gpu()
@@ -235,13 +262,15 @@ def test_unregistered_segment_and_batch_limits():
     ctx.close()
 
 
-def test_library_injection_matches_oracle_signal_model():
+@pytest.mark.parametrize("psd", ["same", "network"])
+def test_library_injection_matches_oracle_signal_model(psd):
     """fcas_inject (the benchmark's signal generator) reproduces the oracle's
-    injection, amplitude normalisation included."""
+    injection, amplitude normalisation included (network SNR over detectors
+    with one noise curve or a curve each)."""
     require_gpu()
     import synth
     from oracle import signal as S
-    case = Case("HLVK", 16384, 2048.0, snr=None, noise=False, cfg=15)
+    case = Case("HLVK", 16384, 2048.0, snr=None, noise=False, cfg=15, psd=psd)
     ctx = make_ctx(case, 0, max_batch=1)
     th0 = np.array([2.1, -0.7, 40.0, 1.3])
     prm = dict(psi=0.4, phi_c=1.9, cos_iota=-0.3, tc_sample=5000)

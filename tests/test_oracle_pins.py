@@ -218,13 +218,16 @@ def test_literal_likelihood_maximised_over_amplitudes():
 
 # ---------------------------------------------------------------- end to end
 
-@pytest.mark.parametrize("names,n,fs", [("HL", 8192, 1024.0), ("HLV", 4096, 2048.0), ("HLVK", 8192, 2048.0)])
-def test_noiseless_injection_identity(names, n, fs):
+@pytest.mark.parametrize("names,n,fs,psd", [("HL", 8192, 1024.0, "same"), ("HLV", 4096, 2048.0, "same"),
+                                            ("HLVK", 8192, 2048.0, "same"), ("HLVK", 8192, 2048.0, "network"),
+                                            ("HL", 4096, 2048.0, "network")])
+def test_noiseless_injection_identity(names, n, fs, psd):
     """Noiseless signal at the true parameters: Gamma^2 = SNR^2 and the maximum
     sits at the injected coalescence sample, for random sky, polarisation,
-    phase and inclination."""
+    phase and inclination, with one noise curve or a different one per
+    detector."""
     for r in range(3):
-        case = Case(names, n, fs, snr=11.0, noise=False, cfg=95, realization=r)
+        case = Case(names, n, fs, snr=11.0, noise=False, cfg=95, realization=r, psd=psd)
         g, j = case.fitness(case.theta0)
         assert g == pytest.approx(121.0, rel=1e-10)
         assert j == case.inj["tc_sample"]
@@ -256,13 +259,15 @@ def test_symmetries_roll_scale_phase():
     assert j2 == j0
 
 
-def test_noise_only_statistics_chi2():
+@pytest.mark.parametrize("kind", ["same", "network"])
+def test_noise_only_statistics_chi2(kind):
     """Under noise only, at fixed theta and j, Gamma^2_j is chi^2 with 4 degrees
     of freedom for a rank-2 network (mean 4, variance 8) and E|z^i_j|^2 = 2:
-    pins the normalisation sigma and the factor 4 df of over-whitening."""
+    pins the normalisation sigma and the factor 4 df of over-whitening, also
+    when every detector has its own noise curve (its own sigma_i)."""
     n, fs = 1024, 512.0
     net = synth.network("HLV")
-    psd = synth.psd_matrix(3, n, fs)
+    psd = synth.psd_matrix(3, n, fs) if kind == "same" else synth.psd_network(3, n, fs)
     theta = np.array([1.0, 0.3, 40.0, 1.2])
     vals, zp = [], []
     for r in range(3000):
