@@ -50,9 +50,9 @@ def parse():
                          "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source; "
                          "sweep: fitness batches of 320 to 20480 points; hour: the PSO search of one hour-long "
                          "segment (7,372,800 samples per detector, three-pass FFT)")
-    ap.add_argument("--hour-workspace-gib", type=float, default=0.0,
-                    help="hour: FFT workspace in GiB (0: the library default, 8 GiB = 72 points, five launches per "
-                         "pass for 320 points; measured faster than one 37.7 GB workspace for the whole batch)")
+    ap.add_argument("--hour-workspace-gib", type=float, default=4.0,
+                    help="hour: FFT workspace in GiB (0: the library default, 8 GiB = 72 points); 4 GiB = 36 "
+                         "points, nine launches per pass for 320 points, measured fastest of 0.22-37.7 GB")
     ap.add_argument("--launch-counts", action="store_true",
                     help="record the points evaluated by each eager launch (adds a sync per step)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

@@ -22,7 +22,7 @@ import torch
 
 from . import fcas
 
-DEFAULT_LENGTHS = (8192, 65536, 131072, 196608, 262144)
+DEFAULT_LENGTHS = (8192, 65536, 131072, 196608, 262144, 460800, 3686400, 7372800)
 GRIDS = (1024, 2048, 4096)
 # rectangle of component masses in [1, 3] Msun at f_low = 30 Hz
 BOX_LO = (0.0, -math.pi / 2, 15.0336, 0.841913)
@@ -83,8 +83,11 @@ def autotune(lengths=DEFAULT_LENGTHS, n_det=4, fs=2048.0, batch=320, reps=10, gr
         lo, hi = torch.tensor(BOX_LO, dtype=torch.float64), torch.tensor(BOX_HI, dtype=torch.float64)
         theta = (lo + u * (hi - lo)).to(dev)
         seg = torch.zeros(batch, dtype=torch.int32, device=dev)
+        # the long three-pass lengths are timed with the 4 GiB workspace their
+        # searches use (36 hour-long points per launch, measured fastest)
+        ws = min(4 << 30, batch * 2 * n * 8) if n > 262144 else 0
         ctx = fcas.Context(pos, ten, fs=fs, f_low=30.0, f_high=1000.0, box_lo=BOX_LO, box_hi=BOX_HI,
-                           max_batch=batch, max_samples=n, device=device, tuning=None)
+                           max_batch=batch, max_samples=n, device=device, tuning=None, workspace_bytes=ws)
         best = None
         for p in cands:
             for g1 in grids:

@@ -60,15 +60,17 @@ constexpr bool kJointExchange = sizeof(Real) == 4;
 template <typename Real>
 constexpr int kLdsSeries = kJointExchange<Real> ? 2 : 1;
 
-// All stages of both series of one transform; JOINT: both series exchange
-// through LDS together (buf0, buf1), else they take turns in buf0.
+// All stages of the S series (1 or 2) of one transform held in registers;
+// JOINT: two series exchange through LDS together (buf0, buf1), else they take
+// turns in buf0.
 template <typename Real, class PL, int L, int E, class Rad, int I, int Ns, bool HALF, bool WAVE, int PAD,
-          bool JOINT = kJointExchange<Real>>
-__device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* buf0, cplx<Real>* buf1,
+          bool JOINT = kJointExchange<Real>, int S = 2>
+__device__ __forceinline__ void run_stages(cplx<Real> (&v)[S][E], cplx<Real>* buf0, cplx<Real>* buf1,
                                            const cplx<Real>* tw, int t) {
   if constexpr (I < Rad::count) {
     constexpr int R = Rad::value[I];
     constexpr bool LAST = (I == Rad::count - 1);
+    static_assert(!JOINT || S == 2, "a joint exchange needs both series");
     if constexpr (JOINT) {
       stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[0], buf0, tw, t);
       stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[1], buf1, tw, t);
@@ -80,7 +82,7 @@ __device__ __forceinline__ void run_stages(cplx<Real> (&v)[2][E], cplx<Real>* bu
       }
     } else {
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
+      for (int s = 0; s < S; ++s) {
         stage_butterflies<Real, L, E, R, Ns, LAST, HALF && I == 0, PAD>(v[s], buf0, tw, t);
         if constexpr (!LAST) {
           lds_exchange_sync<WAVE>();
@@ -195,32 +197,48 @@ __global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))
 // one pass-1 row, so every load and store instruction moves CM * 8 bytes of
 // contiguous row per transform element (128 bytes at CM = 16).
 // ---------------------------------------------------------------------------
-// Exchange mode and software prefetch of the middle pass.  Measured on the
-// hour-long plans: the series taking turns in LDS (half the LDS, so 5 instead
-// of 2 work-groups per CU) runs 1.75x faster than both at once, and a second
-// register set for prefetching then gains nothing, so neither is used.
+// Exchange mode, series per work item and software prefetch of the middle
+// pass.  Measured on the hour-long plans: the series taking turns in LDS (half
+// the LDS) runs 1.75x faster than both at once; a second register set for
+// prefetching then gains nothing, and neither does one series per work item
+// (117 instead of 240 VGPRs, twice the waves per SIMD, 4% slower): the pass
+// moves its 32 N bytes per point at the rate of a device copy.
 constexpr bool kPassmJoint = false;
+constexpr int kPassmSeries = 2;         // series per work item (1: each series its own item)
 constexpr bool kPassmPrefetch = false;
 template <typename Real>
-constexpr bool kPassmJointFor = kPassmJoint && kJointExchange<Real>;
+constexpr bool kPassmJointFor = kPassmJoint && kJointExchange<Real> && kPassmSeries == 2;
 
-template <typename Real, class PL>
-__device__ __forceinline__ void passm_fetch_item(cplx<Real> (&v)[2][PL::EM], const PassArgs& a, int item, int c,
-                                                 int p) {
-  const int slot = item / PL::TILESM;
-  passm_fetch<Real, PL>(v, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, item - slot * PL::TILESM, c, p);
+// Work item -> (list position in the launch, first series, tile); the items
+// of one point run series by series, tiles in order.
+template <class PL>
+__device__ __forceinline__ void passm_decode(int item, int& slot, int& s0, int& tile) {
+  constexpr int PER_SERIES = PL::TILESM, PER_SLOT = (2 / kPassmSeries) * PL::TILESM;
+  slot = item / PER_SLOT;
+  const int r = item - slot * PER_SLOT;
+  const int g = r / PER_SERIES;
+  s0 = g * kPassmSeries;
+  tile = r - g * PER_SERIES;
 }
 
 template <typename Real, class PL>
-__device__ __forceinline__ void passm_item(cplx<Real> (&v)[2][PL::EM], const PassArgs& a, int item,
+__device__ __forceinline__ void passm_fetch_item(cplx<Real> (&v)[kPassmSeries][PL::EM], const PassArgs& a,
+                                                 int item, int c, int p) {
+  int slot, s0, tile;
+  passm_decode<PL>(item, slot, s0, tile);
+  passm_fetch<Real, PL>(v, (const cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p, s0);
+}
+
+template <typename Real, class PL>
+__device__ __forceinline__ void passm_item(cplx<Real> (&v)[kPassmSeries][PL::EM], const PassArgs& a, int item,
                                            cplx<Real>* buf0, cplx<Real>* buf1, const cplx<Real>* tw, int c, int p) {
-  const int slot = item / PL::TILESM;
-  const int tile = item - slot * PL::TILESM;
+  int slot, s0, tile;
+  passm_decode<PL>(item, slot, s0, tile);
   passm_twiddle_in<Real, PL>(v, tile, c, p);
   run_stages<Real, PL, PL::NM, PL::EM, typename PL::RadM, 0, 1, false, false, kPadM, kPassmJointFor<Real>>(
       v, buf0, buf1, tw, p);
   passm_twiddle_out<Real, PL>(v, tile, c, p);
-  passm_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
+  passm_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p, s0);
 }
 
 // Middle pass on the items of `a` taken by work-group `block` of `nblocks`;
@@ -232,12 +250,12 @@ __device__ __forceinline__ void passm_body(const PassArgs& a, cplx<Real>* lds, c
                                            int nblocks) {
   constexpr int LP = lds_padded_len<kPadM>(PL::NM);
   const int tid = threadIdx.x;
-  const int items = launch_span(a) * PL::TILESM;
+  const int items = launch_span(a) * (2 / kPassmSeries) * PL::TILESM;
   const int c = tid % PL::CM, p = tid / PL::CM;
   cplx<Real>* buf0 = lds + c * LP;
   cplx<Real>* buf1 = kPassmJointFor<Real> ? lds + (PL::CM + c) * LP : buf0;
   if constexpr (kPassmPrefetch) {
-    cplx<Real> va[2][PL::EM], vb[2][PL::EM];
+    cplx<Real> va[kPassmSeries][PL::EM], vb[kPassmSeries][PL::EM];
     int item = block;
     if (item < items) passm_fetch_item<Real, PL>(va, a, item, c, p);
     while (item < items) {
@@ -251,7 +269,7 @@ __device__ __forceinline__ void passm_body(const PassArgs& a, cplx<Real>* lds, c
     }
   } else {
     for (int item = block; item < items; item += nblocks) {
-      cplx<Real> v[2][PL::EM];
+      cplx<Real> v[kPassmSeries][PL::EM];
       passm_fetch_item<Real, PL>(v, a, item, c, p);
       passm_item<Real, PL>(v, a, item, buf0, buf1, tw, c, p);
     }

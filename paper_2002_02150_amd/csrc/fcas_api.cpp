@@ -535,7 +535,7 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
       const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
       if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
       if (pi.nm > 1) {
-        const int gm = std::min(m * pi.tilesm[ctx->prec], ctx->grid2[plan]);
+        const int gm = std::min(m * pi.tilesm[ctx->prec] * (2 / kPassmSeries), ctx->grid2[plan]);
         if ((e = timed_launch(ctx, ctx->t_passm, s, 3, plan, a, gm)) != hipSuccess)
           return hip_fail(e, "middle-pass launch");
       }

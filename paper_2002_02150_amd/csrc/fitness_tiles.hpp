@@ -500,61 +500,63 @@ FCAS_HD void passm_coords(int tile, int c, int& j1, int& k2) {
   k2 = (tile - j1 * KT) * PL::CM + c;
 }
 
-template <typename Real, class PL>
-FCAS_HD void passm_fetch(cplx<Real> (&v)[2][PL::EM], const cplx<Real>* slot, int tile, int c, int p) {
+// The middle-pass functions act on S series held in registers, series s0
+// onwards (S = 2, s0 = 0: both).
+template <typename Real, class PL, int S>
+FCAS_HD void passm_fetch(cplx<Real> (&v)[S][PL::EM], const cplx<Real>* slot, int tile, int c, int p, int s0 = 0) {
   int j1, k2;
   passm_coords<PL>(tile, c, j1, k2);
-  const cplx<Real>* at = slot + (int64_t)j1 * PL::W1 + k2;
+  const cplx<Real>* at = slot + (int64_t)s0 * PL::N + (int64_t)j1 * PL::W1 + k2;
 #pragma unroll
   for (int q = 0; q < PL::EM; ++q) {
     const int o = (p + q * PL::PM) * PL::N2;
-    v[0][q] = stream_load(at + o);
-    v[1][q] = stream_load(at + PL::N + o);
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s][q] = stream_load(at + s * PL::N + o);
   }
 }
 
 // w_N^{j1 (km N2 + k2)} on input: exact at q = 0, then advanced by
 // w_N^{j1 PM N2} from register to register.
-template <typename Real, class PL>
-FCAS_HD void passm_twiddle_in(cplx<Real> (&v)[2][PL::EM], int tile, int c, int p) {
+template <typename Real, class PL, int S>
+FCAS_HD void passm_twiddle_in(cplx<Real> (&v)[S][PL::EM], int tile, int c, int p) {
   int j1, k2;
   passm_coords<PL>(tile, c, j1, k2);
   cplx<Real> t = twiddle<Real>(j1 * (p * PL::N2 + k2), (int)PL::N);     // < N1 W1 = N
   const cplx<Real> st = twiddle<Real>(j1 * (PL::PM * PL::N2), (int)PL::N);
 #pragma unroll
   for (int q = 0; q < PL::EM; ++q) {
-    v[0][q] = mul(v[0][q], t);
-    v[1][q] = mul(v[1][q], t);
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s][q] = mul(v[s][q], t);
     if (q + 1 < PL::EM) t = mul(t, st);
   }
 }
 
 // w_{NM N2}^{jm k2} on output: exact at q = 0, then advanced by w_{NM N2}^{PM k2}.
-template <typename Real, class PL>
-FCAS_HD void passm_twiddle_out(cplx<Real> (&v)[2][PL::EM], int tile, int c, int p) {
+template <typename Real, class PL, int S>
+FCAS_HD void passm_twiddle_out(cplx<Real> (&v)[S][PL::EM], int tile, int c, int p) {
   int j1, k2;
   passm_coords<PL>(tile, c, j1, k2);
   cplx<Real> t = twiddle<Real>(p * k2, PL::W1);                      // < PM N2 <= W1
   const cplx<Real> st = twiddle<Real>(PL::PM * k2, PL::W1);
 #pragma unroll
   for (int q = 0; q < PL::EM; ++q) {
-    v[0][q] = mul(v[0][q], t);
-    v[1][q] = mul(v[1][q], t);
+#pragma unroll
+    for (int s = 0; s < S; ++s) v[s][q] = mul(v[s][q], t);
     if (q + 1 < PL::EM) t = mul(t, st);
   }
 }
 
 // Store B2[m][j1][jm N2 + k2], over the elements the tile loaded.
-template <typename Real, class PL>
-FCAS_HD void passm_store(cplx<Real> (&v)[2][PL::EM], cplx<Real>* slot, int tile, int c, int p) {
+template <typename Real, class PL, int S>
+FCAS_HD void passm_store(cplx<Real> (&v)[S][PL::EM], cplx<Real>* slot, int tile, int c, int p, int s0 = 0) {
   int j1, k2;
   passm_coords<PL>(tile, c, j1, k2);
-  cplx<Real>* at = slot + (int64_t)j1 * PL::W1 + k2;
+  cplx<Real>* at = slot + (int64_t)s0 * PL::N + (int64_t)j1 * PL::W1 + k2;
 #pragma unroll
   for (int q = 0; q < PL::EM; ++q) {
     const int o = (p + q * PL::PM) * PL::N2;
-    stream_store(at + o, v[0][q]);
-    stream_store(at + PL::N + o, v[1][q]);
+#pragma unroll
+    for (int s = 0; s < S; ++s) stream_store(at + s * PL::N + o, v[s][q]);
   }
 }
 

@@ -156,8 +156,11 @@ def run_single_segment(minutes=60.0, iters=1000, runs=RUNS, seed=7, snr=(10.0, 1
     inj["snr"] = float(rng.uniform(*snr))
     inj["tau0"], inj["tau15"] = chirp_times(inj["m1"], inj["m2"], F_LOW)
     t_series = time.perf_counter() - t0
+    # a 4 GiB workspace (36 points of an hour per launch) measured fastest: the
+    # later passes then find more of their input in the caches
     ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo_box, box_hi=hi_box,
-                               max_batch=runs * PARTICLES, max_segments=1, max_samples=total)
+                               max_batch=runs * PARTICLES, max_segments=1, max_samples=total,
+                               workspace_bytes=min(4 << 30, runs * PARTICLES * 2 * total * 8))
     psd = torch.from_numpy(synth.psd_matrix(D, total, FS)).to(dev)
     t1 = time.perf_counter()
     xf = torch.from_numpy(np.stack([synth.segment_fd(series[i], 0, total, FS) for i in range(D)])).to(dev)
