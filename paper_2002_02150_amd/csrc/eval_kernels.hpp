@@ -100,13 +100,23 @@ __device__ __forceinline__ void run_stages(cplx<Real> (&v)[S][E], cplx<Real>* bu
 // segment data stay in the L2 anyway; tile-major for the long three-pass
 // segments (112 MB of data at one hour), so that the work-groups in flight
 // take one tile of many points and share its data in the cache instead of
-// each point re-reading the whole segment from HBM.
+// each point re-reading the whole segment from HBM.  Work-groups are handed
+// to the 8 XCDs in turn, so with a grid that is a multiple of 8, items that
+// agree mod 8 run on one XCD: the tile-major order then gives XCD x the tiles
+// x, x + 8, ... (when 8 divides TILES1), and each XCD's L2 fetches an eighth
+// of the segment instead of all of it (pass 1 3% faster at one hour).  Any
+// grid gives the same results: only the order of the items changes.
 template <class PL>
 constexpr bool kTileMajor1 = PL::THREE;
 
 template <class PL>
 __device__ __forceinline__ void pass1_decode(int item, int span, int& slot, int& tile) {
-  if constexpr (kTileMajor1<PL>) {
+  if constexpr (kTileMajor1<PL> && PL::TILES1 % 8 == 0) {
+    const int x = item & 7, r = item >> 3;
+    const int g = r / span;
+    slot = r - g * span;
+    tile = x + 8 * g;
+  } else if constexpr (kTileMajor1<PL>) {
     tile = item / span;
     slot = item - tile * span;
   } else {

@@ -60,6 +60,9 @@ def _run(emu, tmp_path, case, theta, plan, prec):
     (18, "HLVK", 0), (19, "HL", 0), (12, "HLVK", 1), (18, "HL", 1), (20, "HLVK", 0), (20, "HL", 1),
     (21, "HLVK", 0), (22, "HLV", 0), (23, "HLVK", 0), (24, "HLVK", 0), (21, "HL", 1), (24, "HL", 1),
     (25, "HLVK", 0), (25, "HL", 1), (27, "HLVK", 0), (29, "HL", 1),
+    # five and six detectors (a site repeated: a co-located pair with its own
+    # noise) take the kernels' run-time detector loop
+    (6, "HLVKH", 0), (25, "HLVKHL", 0), (2, "HLVKHL", 1),
 ])
 def test_emulated_path_matches_oracle(emu, tmp_path, plan, names, prec):
     n = PLANS[plan]

@@ -18,6 +18,9 @@ pytestmark = pytest.mark.gpu
 SMALL = [  # (N, fs, detectors)
     (2048, 1024.0, "HL"), (4096, 2048.0, "HLV"), (8192, 1024.0, "HL"), (16384, 2048.0, "HLVK"),
     (32768, 2048.0, "L"), (24576, 2048.0, "HLV"), (49152, 2048.0, "HLVK"),
+    # five and six detectors (a repeated site is a co-located pair with independent
+    # noise): the kernels' run-time detector loop
+    (16384, 2048.0, "HLVKH"), (8192, 1024.0, "HLVKHL"),
 ]
 
 

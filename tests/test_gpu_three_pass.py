@@ -31,12 +31,13 @@ def _eval(ctx, th, seg=0):
     return f.cpu().numpy(), j.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", [0, 1], ids=["mixed", "fp64"])
-def test_three_pass_225s_matches_oracle(prec):
+@pytest.mark.parametrize("names,prec", [("HLVK", 0), ("HLVK", 1), ("L", 0), ("HLVKHL", 0)],
+                         ids=["HLVK-mixed", "HLVK-fp64", "L-mixed", "HLVKHL-mixed"])
+def test_three_pass_225s_matches_oracle(names, prec):
     """460,800 samples: every point of a batch with near, uniform, corner and
-    outside-the-rectangle points."""
+    outside-the-rectangle points, for one to six detectors."""
     require_gpu()
-    case = Case("HLVK", 460800, 2048.0, snr=12.0, cfg=30, realization=prec)
+    case = Case(names, 460800, 2048.0, snr=12.0, cfg=30, realization=prec)
     rng = np.random.default_rng(250 + prec)
     th = thetas_for(case, rng, n_near=6, n_uniform=6)
     ctx = make_ctx(case, prec, max_batch=len(th))
