@@ -6,6 +6,8 @@ L_DP = P(rho' <= eta | rho0 >= eta) (eq. loss_detprob), rho0 being the
 statistic at the true parameters.
 
     python -m paper_2002_02150_amd.detection [--slides 4] [--per-snr 64] [--iters 1000]
+    python -m paper_2002_02150_amd.detection --hour --slides 1-24 [--iters 500] [--runs 12]
+    python -m paper_2002_02150_amd.detection --combine a.json b.json ...
 
 Data: 4 detectors (H, L, V, K), 64-s segments at 2048 Hz, analytic PSD.
 - H0: an hour of seeded Gaussian noise per detector, cut into 56 consecutive
@@ -20,6 +22,14 @@ segments of both sets one batch (campaign.search_segments), then the polish.
 The threshold is taken at a false-alarm probability per segment of
 FAR x T_seg (FAR = 1 per year by default) on the lognormal fitted to rho' by
 maximum likelihood (mean and standard deviation of log rho').
+
+--hour takes the paper's own segment length (Sec. V: one 60-min segment per
+search, false-alarm probability 1.14e-4 per segment for 1 per year): one hour
+of noise per detector, slide s = a..b shifting detector i circularly by
+10 s * s * i, each slide one hour-long noise-only network segment searched
+with the three-pass FFT plan (`group` segments per batch).  It prints the H0
+values rho' of its slides; --combine fits the lognormal to the values of
+several such runs and gives eta.
 """
 from __future__ import annotations
 
@@ -128,15 +138,81 @@ def run(slides=4, per_snr=64, snrs=(9.0, 10.0, 12.0), iters=1000, runs=8, far_pe
                 eta=eta, table=table)
 
 
+HOUR = 7372800
+
+
+def hour_h0(first=1, last=24, iters=500, runs=12, group=8, seed=8, polish_steps=20, log=print):
+    """H0 values rho' of the time-slid hour-long noise-only segments first..last."""
+    import synth
+    dev = torch.device("cuda", 0)
+    net = synth.network("HLVK")
+    D = net.n_det
+    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    series = np.stack([synth.td_noise(np.random.default_rng(synth.seed_sequence(seed, 0, i)), HOUR, FS)
+                       for i in range(D)])
+    psd = torch.from_numpy(synth.psd_matrix(D, HOUR, FS)).to(dev)
+    rho, seconds = {}, 0.0
+    for g0 in range(first, last + 1, group):
+        slides = list(range(g0, min(g0 + group, last + 1)))
+        n = len(slides) * runs * 40
+        ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
+                                   max_segments=len(slides), max_samples=HOUR,
+                                   workspace_bytes=min(16 << 30, n * 2 * HOUR * 8))
+        for k, s in enumerate(slides):
+            xf = np.stack([synth.segment_fd(np.roll(series[i], -int(round(SLIDE_S * FS)) * s * i), 0, HOUR, FS)
+                           for i in range(D)])
+            ctx.set_segment(k, torch.from_numpy(xf).to(dev), psd)
+        torch.cuda.synchronize()
+        res = search_segments(ctx, len(slides), runs, 40, iters, seed=20020215 + seed + g0,
+                              polish_steps=polish_steps, log=log)
+        seconds += res["seconds"]
+        for k, s in enumerate(slides):
+            rho[s] = float(np.sqrt(max(res["rho_sq"][k].item(), 0.0)))
+        ctx.close()
+        log(f"slides {slides[0]}-{slides[-1]}: rho' " + " ".join(f"{rho[s]:.3f}" for s in slides))
+    return dict(segment_samples=HOUR, slides=[first, last], iterations=iters, runs=runs, seconds_search=seconds,
+                rho=rho)
+
+
+def combine(outs, far_per_year=1.0):
+    """Lognormal fit of the H0 values of several hour_h0 runs and the threshold."""
+    rho = {}
+    for o in outs:
+        rho.update({int(k): v for k, v in o["rho"].items()})
+    vals = np.array([rho[k] for k in sorted(rho)])
+    p_fa = far_per_year * HOUR / FS / YEAR_S
+    eta, mu, sd, ks_p = lognormal_threshold(vals, p_fa)
+    return dict(segments_h0=len(vals), p_false_alarm_per_segment=p_fa, eta=eta,
+                h0_lognormal=dict(mu=mu, sigma=sd, ks_pvalue=ks_p),
+                h0_rho_quantiles={q: float(np.quantile(vals, q)) for q in (0.05, 0.5, 0.95, 1.0)},
+                iterations=sorted({o["iterations"] for o in outs}), runs=sorted({o["runs"] for o in outs}))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--slides", type=int, default=4)
+    ap.add_argument("--slides", default="4", help="time slides (an int), or a-b with --hour")
     ap.add_argument("--per-snr", type=int, default=64)
-    ap.add_argument("--iters", type=int, default=1000)
+    ap.add_argument("--iters", type=int, default=None, help="PSO iterations (1000; 500 with --hour)")
     ap.add_argument("--snrs", default="9,10,12")
+    ap.add_argument("--hour", action="store_true", help="H0 of time-slid hour-long segments (slides a-b)")
+    ap.add_argument("--runs", type=int, default=None)
+    ap.add_argument("--combine", nargs="+", default=None, help="JSON outputs of --hour runs to fit together")
     a = ap.parse_args(argv)
-    out = run(a.slides, a.per_snr, tuple(float(x) for x in a.snrs.split(",")), a.iters,
-              log=lambda s: print(s, flush=True))
+    log = lambda s: print(s, flush=True)
+    if a.combine:
+        outs = []
+        for path in a.combine:
+            with open(path) as fh:
+                outs.append(json.loads([l for l in fh if l.startswith("{")][-1]))
+        print(json.dumps(combine(outs)))
+        return 0
+    if a.hour:
+        first, last = (int(x) for x in str(a.slides).split("-"))
+        out = hour_h0(first, last, iters=a.iters or 500, runs=a.runs or 12, log=log)
+        print(json.dumps(out))
+        return 0
+    out = run(int(a.slides), a.per_snr, tuple(float(x) for x in a.snrs.split(",")), a.iters or 1000,
+              runs=a.runs or 8, log=log)
     print(json.dumps(out))
     return 0
 

@@ -282,6 +282,8 @@ class Context:
         _check(library().fcas_set_timing(self._h, 1 if on else 0))
 
     def read_timing(self, which):
+        """(total ms, launches) of the FFT kernel `which` ("pass1", "passm",
+        "pass2" or "fused") since timing was enabled; resets the record."""
         ms = ctypes.c_double(0)
         cnt = ctypes.c_int64(0)
         _check(library().fcas_read_timing(self._h, which.encode(), ctypes.byref(ms), ctypes.byref(cnt)))

@@ -181,6 +181,18 @@ def test_single_segment_search_small():
     assert abs(d["rho0_sq"] / d["snr"] ** 2 - 1.0) < 0.5
 
 
+def test_hour_h0_small():
+    """The hour-long H0 mode (time-slid 7,372,800-sample noise segments,
+    three-pass FFT) runs end to end for two slides and its values combine into
+    a threshold."""
+    require_gpu()
+    from paper_2002_02150_amd.detection import combine, hour_h0
+    out = hour_h0(1, 2, iters=6, runs=1, group=2, polish_steps=1, log=lambda s: None)
+    assert sorted(out["rho"]) == [1, 2] and all(v > 0 for v in out["rho"].values())
+    c = combine([out])
+    assert c["segments_h0"] == 2 and c["eta"] > max(out["rho"].values())
+
+
 def test_detection_study_small():
     """The detection-statistics study (time-slid noise-only segments, injected
     segments, one batched search, lognormal threshold, detection probability

@@ -93,3 +93,4 @@ def test_swarm_converges_on_smooth_peak():
     bf, bx, _, _ = pso.best_of_runs(st, lo, hi)
     assert np.linalg.norm(bx - centre) < 1e-2
     assert bf > 10.0 - 1e-4
+
