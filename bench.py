@@ -14,6 +14,11 @@ same points are compared with it (parity: relative error of the fitness,
 argmax agreement).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
+
+Other workloads (--config): hour (the paper's own segment length: one hour at
+2048 Hz, 7,372,800 samples per detector, three-pass FFT plan, the same PSO
+step and polish, per-pass rooflines), batched (256 ragged segments), gradient
+(4096 fitness gradients), sweep (batch sizes 320-20480).
 """
 import argparse
 import hashlib

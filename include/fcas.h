@@ -58,7 +58,8 @@ extern "C" {
 #define FCAS_FP64 1   /* everything in FP64 (the plain reference path)            */
 
 /* launch schedule of the FFT passes (FUSED: FCAS_MIXED only; an FCAS_FP64
- * context runs TWO_PASS, and so do the three-pass plans under FUSED) */
+ * context runs TWO_PASS, and so do, under FUSED, the three-pass plans and the
+ * plans whose two passes use work-groups of different sizes) */
 #define FCAS_SCHEDULE_FUSED 0     /* one persistent launch per plan, passes pipelined  */
 #define FCAS_SCHEDULE_TWO_PASS 1  /* a pass-1 and a pass-2 launch per workspace chunk
                                      (the faster one on MI355X: recommended)          */

@@ -507,8 +507,8 @@ int enqueue_fused(fcas_ctx* ctx, int plan, int n, int cap, hipStream_t s) {
 }
 
 // Enqueues set-up, the FFT passes of every plan in use, and finalize.  Plans
-// with a middle pass always run as separate launches (the fused schedule
-// covers two-pass plans).
+// with a middle pass, or with passes of unequal work items, always run as
+// separate launches (the fused schedule covers the other two-pass plans).
 int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
                  int32_t* d_argmax, hipStream_t s) {
   hipError_t e;
@@ -523,7 +523,7 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
     const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
     int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
     if (cap < 1) cap = 1;
-    if (ctx->schedule == FCAS_SCHEDULE_FUSED && pi.nm == 1) {
+    if (ctx->schedule == FCAS_SCHEDULE_FUSED && pi.nm == 1 && pi.threads1[0] == pi.threads2[0]) {
       if ((rc = enqueue_fused(ctx, plan, n, cap, s))) return rc;
       continue;
     }

@@ -29,7 +29,11 @@ hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* 
 
 // Per-plan launch helpers of the per-precision translation units: the middle
 // pass exists only for three-pass plans, the fused kernel only for two-pass
-// ones; asked for the other kind they return hipErrorInvalidValue.
+// plans whose passes have equal work items (kFusable); asked for another plan
+// they return hipErrorInvalidValue.
+template <class PL>
+constexpr bool kFusable = !PL::THREE && PL::T1 == PL::T2;
+
 template <typename Real, class PL>
 hipError_t launch_passm_plan(const PassArgs& a, int grid, hipStream_t s) {
   if constexpr (PL::THREE) {
@@ -42,7 +46,7 @@ hipError_t launch_passm_plan(const PassArgs& a, int grid, hipStream_t s) {
 
 template <class PL>
 hipError_t launch_fused_plan(const FusedArgs& f, int grid, hipStream_t s) {
-  if constexpr (!PL::THREE) {
+  if constexpr (kFusable<PL>) {
     hipLaunchKernelGGL((k_fused<float, PL>), dim3(grid), dim3(PL::T1), 0, s, f);
     return hipGetLastError();
   } else {
@@ -53,7 +57,7 @@ hipError_t launch_fused_plan(const FusedArgs& f, int grid, hipStream_t s) {
 template <class PL>
 int fused_occupancy_plan() {
   int nb = 0;
-  if constexpr (!PL::THREE) {
+  if constexpr (kFusable<PL>) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)k_fused<float, PL>, PL::T1, 0) != hipSuccess)
       nb = 0;
   }
