@@ -8,6 +8,8 @@ statistic at the true parameters.
     python -m paper_2002_02150_amd.detection [--slides 4] [--per-snr 64] [--iters 1000]
     python -m paper_2002_02150_amd.detection --hour --slides 1-24 [--iters 500] [--runs 12]
     python -m paper_2002_02150_amd.detection --combine a.json b.json ...
+    python -m paper_2002_02150_amd.detection --hour-h1 --snr 10 --segments 0-7 [--iters 1500]
+    python -m paper_2002_02150_amd.detection --h1-table ETA h1a.json h1b.json ...
 
 Data: 4 detectors (H, L, V, K), 64-s segments at 2048 Hz, analytic PSD.
 - H0: an hour of seeded Gaussian noise per detector, cut into 56 consecutive
@@ -29,7 +31,10 @@ of noise per detector, slide s = a..b shifting detector i circularly by
 10 s * s * i, each slide one hour-long noise-only network segment searched
 with the three-pass FFT plan (`group` segments per batch).  It prints the H0
 values rho' of its slides; --combine fits the lognormal to the values of
-several such runs and gives eta.
+several such runs and gives eta.  --hour-h1 searches hour-long segments of
+independent noise with one SPA injection each at a network SNR and prints rho'
+and rho0 (the statistic at the true parameters); --h1-table gives, for a
+threshold eta, the detection probability and L_DP per SNR.
 """
 from __future__ import annotations
 
@@ -174,6 +179,68 @@ def hour_h0(first=1, last=24, iters=500, runs=12, group=8, seed=8, polish_steps=
                 rho=rho)
 
 
+def hour_h1(snr, first=0, last=7, iters=1500, runs=12, group=8, seed=9, polish_steps=20, log=print):
+    """rho' and rho0 of hour-long segments first..last: independent Gaussian
+    noise (seeded per segment) with one SPA injection at network SNR `snr`
+    (masses U[1, 3] Msun, isotropic sky and orientation, coalescence in the
+    middle half of the hour)."""
+    import synth
+    dev = torch.device("cuda", 0)
+    net = synth.network("HLVK")
+    D = net.n_det
+    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    psd_np = synth.psd_matrix(D, HOUR, FS)
+    psd = torch.from_numpy(psd_np).to(dev)
+    out, seconds = {}, 0.0
+    for g0 in range(first, last + 1, group):
+        idx = list(range(g0, min(g0 + group, last + 1)))
+        n = len(idx) * runs * 40
+        ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
+                                   max_segments=len(idx), max_samples=HOUR,
+                                   workspace_bytes=min(16 << 30, n * 2 * HOUR * 8))
+        truth = []
+        for k, r in enumerate(idx):
+            rng = np.random.default_rng(synth.seed_sequence(seed, int(round(10 * snr)), 5000 + r))
+            inj = synth.draw_injection(rng, HOUR)
+            inj["tc_sample"] = int(rng.integers(HOUR // 4, 3 * HOUR // 4))
+            t0, t15 = chirp_times(inj["m1"], inj["m2"], F_LOW)
+            x = torch.from_numpy(synth.noise_matrix(seed, 1000 * int(round(10 * snr)) + r, psd_np, HOUR, FS)).to(dev)
+            ctx.inject(x, psd, inj["alpha"], inj["delta"], t0, t15, inj["psi"], inj["phi_c"], inj["cos_iota"],
+                       inj["tc_sample"] / FS, snr)
+            ctx.set_segment(k, x, psd)
+            truth.append([inj["alpha"], inj["delta"], t0, t15])
+        torch.cuda.synchronize()
+        res = search_segments(ctx, len(idx), runs, 40, iters, seed=20020215 + seed + 7 * g0,
+                              polish_steps=polish_steps, log=log)
+        seconds += res["seconds"]
+        th0 = torch.tensor(truth, dtype=torch.float64, device=dev)
+        f0 = ctx.eval(th0, torch.arange(len(idx), dtype=torch.int32, device=dev))[0].cpu().numpy()
+        for k, r in enumerate(idx):
+            out[r] = dict(rho=float(np.sqrt(max(res["rho_sq"][k].item(), 0.0))), rho0=float(np.sqrt(max(f0[k], 0.0))))
+        ctx.close()
+        log(f"SNR {snr:g} segments {idx[0]}-{idx[-1]}: " + " ".join(f"{out[r]['rho']:.2f}/{out[r]['rho0']:.2f}" for r in idx))
+    return dict(segment_samples=HOUR, snr=snr, segments=[first, last], iterations=iters, runs=runs,
+                seconds_search=seconds, values=out)
+
+
+def h1_table(eta, outs):
+    """Detection probability P(rho' >= eta) and L_DP = P(rho' <= eta | rho0 >= eta) per SNR."""
+    by = {}
+    for o in outs:
+        by.setdefault(o["snr"], {}).update(o["values"])
+    table = []
+    for snr in sorted(by):
+        v = list(by[snr].values())
+        r1 = np.array([x["rho"] for x in v])
+        r0 = np.array([x["rho0"] for x in v])
+        above0 = r0 >= eta
+        table.append(dict(snr=snr, segments=len(v), detection_probability=float(np.mean(r1 >= eta)),
+                          l_dp=float(np.mean(r1[above0] <= eta)) if above0.any() else None,
+                          truth_above_eta=int(above0.sum()), pso_below_truth=float(np.mean(r1 < r0)),
+                          median_rho=float(np.median(r1)), median_rho0=float(np.median(r0))))
+    return dict(eta=eta, table=table)
+
+
 def combine(outs, far_per_year=1.0):
     """Lognormal fit of the H0 values of several hour_h0 runs and the threshold."""
     rho = {}
@@ -197,8 +264,24 @@ def main(argv=None):
     ap.add_argument("--hour", action="store_true", help="H0 of time-slid hour-long segments (slides a-b)")
     ap.add_argument("--runs", type=int, default=None)
     ap.add_argument("--combine", nargs="+", default=None, help="JSON outputs of --hour runs to fit together")
+    ap.add_argument("--hour-h1", action="store_true", help="hour-long segments with an injection at --snr")
+    ap.add_argument("--snr", type=float, default=10.0)
+    ap.add_argument("--segments", default="0-7", help="--hour-h1: segment indices a-b")
+    ap.add_argument("--h1-table", nargs="+", default=None, help="ETA, then JSON outputs of --hour-h1 runs")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
+    if a.h1_table:
+        outs = []
+        for path in a.h1_table[1:]:
+            with open(path) as fh:
+                outs.append(json.loads([l for l in fh if l.startswith("{")][-1]))
+        print(json.dumps(h1_table(float(a.h1_table[0]), outs)))
+        return 0
+    if a.hour_h1:
+        first, last = (int(x) for x in a.segments.split("-"))
+        out = hour_h1(a.snr, first, last, iters=a.iters or 1500, runs=a.runs or 12, log=log)
+        print(json.dumps(out))
+        return 0
     if a.combine:
         outs = []
         for path in a.combine:

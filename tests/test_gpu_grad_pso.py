@@ -193,6 +193,16 @@ def test_hour_h0_small():
     assert c["segments_h0"] == 2 and c["eta"] > max(out["rho"].values())
 
 
+def test_hour_h1_small():
+    """The hour-long H1 mode (an injection in an hour of noise, three-pass FFT,
+    rho' and rho0) runs end to end for one segment."""
+    require_gpu()
+    from paper_2002_02150_amd.detection import hour_h1
+    out = hour_h1(12.0, 0, 0, iters=6, runs=1, polish_steps=1, log=lambda s: None)
+    v = out["values"][0]
+    assert v["rho"] > 0 and v["rho0"] > 0 and out["snr"] == 12.0
+
+
 def test_detection_study_small():
     """The detection-statistics study (time-slid noise-only segments, injected
     segments, one batched search, lognormal threshold, detection probability
