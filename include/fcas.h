@@ -137,7 +137,12 @@ int fcas_select_plan(fcas_ctx* ctx, int32_t plan, int32_t grid1, int32_t grid2);
  * The library stores sigma_i^2 = 4 df sum_B f^-7/3 / S^i and
  * y^i_k = 4 df x^i_k f_k^-7/6 / (S^i_k sigma_i) for the in-band bins.  The
  * inputs may be freed once the call returns; it synchronises `hip_stream`.
- * Not capturable. */
+ * Not capturable.  Errors: FCAS_ENOSEG (id out of range),
+ * FCAS_EUNSUPPORTED_N / FCAS_EINVAL (length, NULL pointer, empty band, a
+ * template norm sigma_i^2 that is not positive and finite, e.g. a zero or
+ * non-finite PSD value in band), FCAS_ENOMEM, FCAS_EHIP.  A call that fails
+ * after its arguments were validated leaves seg_id unregistered, also when
+ * it was registered before (evaluations of it then give NaN, -2). */
 int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples,
                      const double* d_xf, const double* d_psd, void* hip_stream);
 
@@ -230,6 +235,21 @@ int pso_step(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s,
 int pso_best(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s,
              double* d_out_f, double* d_out_theta, int32_t* d_out_j, int32_t* d_out_run,
              void* hip_stream);
+
+/* Best of the runs of each segment (Sec. III) when one swarm searches several
+ * segments: runs g*runs_per_segment .. (g+1)*runs_per_segment - 1 belong to
+ * segment g, for g = 0 .. n_runs/runs_per_segment - 1, and the best is taken
+ * over the first runs_used of them (runs_used = runs_per_segment: all; fewer
+ * give the statistic of a search with fewer runs, as the tuning metric of
+ * Sec. III compares).  Per segment g: d_out_f[g] float64 (its coherent search
+ * statistic squared), d_out_theta[g] float64 [4] (rectangle coordinates),
+ * d_out_j[g] int32 (coalescence sample), d_out_run[g] int32 (index of the best
+ * run in the swarm, the lowest on ties).  FCAS_EINVAL unless
+ * runs_per_segment >= 1 divides n_runs and 1 <= runs_used <= runs_per_segment.
+ * Asynchronous; capturable. */
+int pso_best_segments(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, int32_t runs_per_segment,
+                      int32_t runs_used, double* d_out_f, double* d_out_theta, int32_t* d_out_j, int32_t* d_out_run,
+                      void* hip_stream);
 
 /* Synthetic input (the signal model of Sec. II eq. detresponse with the SPA
  * polarisations of Sec. II.B): adds to d_xf (complex128 [n_det][N/2+1], raw

@@ -54,13 +54,8 @@ def search_segments(ctx, n_seg, runs=8, particles=40, iters=2000, seed=20020215,
             log(f"iteration {1 + (g + 1) * group}: {time.perf_counter() - t0:.1f} s")
     for _ in range(rest % group):
         graph1.replay()
-    best_f = sw.best_f.view(n_seg, runs)
-    k = torch.argmax(best_f, dim=1)
-    rows = torch.arange(n_seg, device=dev) * runs + k
-    lo = torch.tensor(ctx.box_lo, dtype=torch.float64, device=dev)
-    span = torch.tensor(ctx.box_hi, dtype=torch.float64, device=dev) - lo
-    theta = (lo + sw.best_x[rows] * span).contiguous()
-    f_pso = best_f.gather(1, k[:, None])[:, 0].clone()
+    # best of each segment's runs, in the library (pso_best_segments)
+    f_pso, theta, _, _ = sw.best_segments(runs)
     seg_best = torch.arange(n_seg, device=dev, dtype=torch.int32)
     if polish_steps > 0:
         theta, f_pol, j_pol = polish(ctx, theta, seg_best, steps=polish_steps, step_frac=1e-3, trials=trials)

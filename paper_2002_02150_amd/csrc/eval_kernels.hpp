@@ -7,7 +7,41 @@
 #include "fitness_tiles.hpp"
 #include "plans.hpp"
 
+// Build-time overrides of the pass kernels' settings (-1: the per-plan
+// choice of PassTune below): software prefetch of the next work item's data
+// (1) or a fetch at the start of each item (0), and the occupancy each pass
+// kernel is compiled for (waves per SIMD; 1 = no bound below the register
+// file's).
+#ifndef FCAS_PASS1_PREFETCH
+#define FCAS_PASS1_PREFETCH (-1)
+#endif
+#ifndef FCAS_PASS1_WAVES
+#define FCAS_PASS1_WAVES (-1)
+#endif
+#ifndef FCAS_PASS2_PREFETCH
+#define FCAS_PASS2_PREFETCH (-1)
+#endif
+#ifndef FCAS_PASS2_WAVES
+#define FCAS_PASS2_WAVES (-1)
+#endif
+
 namespace fcas {
+
+// Settings of the pass kernels of one plan.  Float transforms of 8-element
+// threads fit in 128 VGPRs without a prefetch register set: at 4 waves per
+// SIMD (their LDS allows 4 work-groups of 4 waves per CU) they run faster
+// than at 3 waves with the next item prefetched (measured on the 4 x 131072
+// search: pass 1 -7%, pass 2 -10%); the other plans (16-element threads,
+// double precision) keep the prefetch at their register-bound occupancy.
+template <typename Real, class PL>
+struct PassTune {
+  static constexpr bool light1 = sizeof(Real) == 4 && PL::E1 == 8;
+  static constexpr bool light2 = sizeof(Real) == 4 && PL::E2 == 8;
+  static constexpr bool prefetch1 = FCAS_PASS1_PREFETCH >= 0 ? FCAS_PASS1_PREFETCH != 0 : !light1;
+  static constexpr bool prefetch2 = FCAS_PASS2_PREFETCH >= 0 ? FCAS_PASS2_PREFETCH != 0 : !light2;
+  static constexpr int waves1 = FCAS_PASS1_WAVES >= 0 ? FCAS_PASS1_WAVES : (light1 ? 4 : 3);
+  static constexpr int waves2 = FCAS_PASS2_WAVES >= 0 ? FCAS_PASS2_WAVES : (light2 ? 4 : 1);
+};
 
 struct PassArgs {
   const SegDesc* segs;
@@ -125,13 +159,22 @@ __device__ __forceinline__ void pass1_decode(int item, int span, int& slot, int&
   }
 }
 
+// Point (evaluation index) at list position `pos` of the launch, and its
+// segment's descriptor: uniform across the work-group, read as scalar loads.
+__device__ __forceinline__ int list_entry(const PassArgs& a, int pos) { return *const_view(a.list + pos); }
+
+__device__ __forceinline__ SegDesc segment_of(const PassArgs& a, int e) {
+  const int seg = const_view(a.evals + e)->seg;
+  return *const_view(a.segs + seg);
+}
+
 template <typename Real, class PL, int DT>
 __device__ __forceinline__ void pass1_fetch_item(Pass1Data<Real, PL, DT>& d, const PassArgs& a, int item, int span,
                                                  int c, int p) {
   int slot, tile;
   pass1_decode<PL>(item, span, slot, tile);
-  const EvalDesc& ev = a.evals[a.list[a.chunk_begin + slot]];
-  pass1_fetch<Real, PL, DT>(d, a.segs[ev.seg], tile, c, p);
+  const SegDesc sg = segment_of(a, list_entry(a, a.chunk_begin + slot));
+  pass1_fetch<Real, PL, DT>(d, sg, tile, c, p);
 }
 
 // LDS exchange buffers of the two passes: padded length of one transform and
@@ -154,7 +197,19 @@ __device__ __forceinline__ void pass1_body(const PassArgs& a, cplx<Real>* lds, c
   const int c = tid % PL::C, p = tid / PL::C;
   cplx<Real>* buf0 = lds + c * LP;
   cplx<Real>* buf1 = kJointExchange<Real> ? lds + (PL::C + c) * LP : buf0;
-  if constexpr (DT > 0) {
+  if constexpr (DT > 0 && !PassTune<Real, PL>::prefetch1) {
+    // each item fetches its own segment data; other waves cover the latency
+    for (int item = block; item < items; item += nblocks) {
+      int slot, tile;
+      pass1_decode<PL>(item, span, slot, tile);
+      Pass1Data<Real, PL, DT> d;
+      pass1_fetch_item<Real, PL, DT>(d, a, item, span, c, p);
+      cplx<Real> v[2][PL::E1];
+      pass1_compute<Real, PL, DT>(v, d, pass1_point<Real, DT>(const_view(a.evals + list_entry(a, a.chunk_begin + slot))));
+      run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, false, kPad1>(v, buf0, buf1, tw, p);
+      pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
+    }
+  } else if constexpr (DT > 0) {
     // software pipeline: once an item's prologue has consumed its segment
     // data, the next item's are fetched while this one is transformed (one set
     // of prefetch registers)
@@ -165,9 +220,12 @@ __device__ __forceinline__ void pass1_body(const PassArgs& a, cplx<Real>* lds, c
       int slot, tile;
       pass1_decode<PL>(item, span, slot, tile);
       cplx<Real> v[2][PL::E1];
-      pass1_compute<Real, PL, DT>(v, d, a.evals[a.list[a.chunk_begin + slot]]);
+      pass1_compute<Real, PL, DT>(v, d, pass1_point<Real, DT>(const_view(a.evals + list_entry(a, a.chunk_begin + slot))));
+      // the fetch is unconditional (the last item re-reads its own data) so
+      // that every path through the loop has the same loads in flight and the
+      // compiler's wait counts never drain the prefetch early
       const int next = item + nblocks;
-      if (next < items) pass1_fetch_item<Real, PL, DT>(d, a, next, span, c, p);
+      pass1_fetch_item<Real, PL, DT>(d, a, next < items ? next : item, span, c, p);
       run_stages<Real, PL, PL::N1, PL::E1, typename PL::Rad1, 0, 1, true, false, kPad1>(v, buf0, buf1, tw, p);
       pass1_store<Real, PL>(v, (cplx<Real>*)a.ws + (int64_t)slot * 2 * PL::N, tile, c, p);
     }
@@ -194,7 +252,8 @@ __device__ __forceinline__ void init_twiddles(cplx<Real>* tw) {
 }
 
 template <typename Real, class PL, int DT>
-__global__ void __launch_bounds__(PL::T1) __attribute__((amdgpu_waves_per_eu(3))) k_pass1(PassArgs a) {
+__global__ void __launch_bounds__(PL::T1)
+    __attribute__((amdgpu_waves_per_eu(PassTune<Real, PL>::waves1))) k_pass1(PassArgs a) {
   __shared__ cplx<Real> lds[PassLds<Real, PL>::X1];
   __shared__ cplx<Real> tw[PL::N1];
   init_twiddles<Real, PL::N1, PL::T1>(tw);
@@ -308,13 +367,13 @@ __device__ __forceinline__ void pass2_item(cplx<Real> (&v)[2][PL::E2], const Pas
   constexpr int NW = PL::T2 / 64;
   const int slot = item / PL::TILES2;
   const int tile = item - slot * PL::TILES2;
-  const int e = a.list[a.chunk_begin + slot];
+  const int e = list_entry(a, a.chunk_begin + slot);
   // row transforms held by one wavefront exchange through LDS without a
   // work-group barrier
   constexpr bool WAVE = (64 % PL::P2) == 0;
   if constexpr (!PL::THREE) pass2_twiddle<Real, PL>(v, tile, r, p);
   run_stages<Real, PL, PL::N2, PL::E2, typename PL::Rad2, 0, 1, false, WAVE, kPad2>(v, buf0, buf1, tw, p);
-  const SegDesc& sg = a.segs[a.evals[e].seg];
+  const SegDesc sg = segment_of(a, e);
   Real g;
   int j;
   pass2_best<Real, PL>(v, tile, r, p, g, j, sg.j_lo, sg.j_hi);
@@ -355,22 +414,35 @@ __device__ __forceinline__ void pass2_body(const PassArgs& a, cplx<Real>* lds, c
   const int lane = tid & 63, wave = tid >> 6;
   // software pipeline over two register sets: the rows of the next item are
   // fetched while this one is transformed
+  // (the fetches are unconditional, a missing next item replaced by one
+  // already fetched, so that every path has the same loads in flight and the
+  // compiler's wait counts only wait for the set being transformed)
+  if constexpr (!PassTune<Real, PL>::prefetch2) {
+    // one register set: each item's rows are loaded when it starts
+    for (int item = block; item < items; item += nblocks) {
+      cplx<Real> v[2][PL::E2];
+      pass2_fetch_item<Real, PL>(v, a, item, r, p);
+      pass2_item<Real, PL>(v, a, item, buf0, buf1, tw, r, p, lane, wave);
+    }
+    return;
+  }
   cplx<Real> va[2][PL::E2], vb[2][PL::E2];
   int item = block;
   if (item < items) pass2_fetch_item<Real, PL>(va, a, item, r, p);
   while (item < items) {
     const int next = item + nblocks;
-    if (next < items) pass2_fetch_item<Real, PL>(vb, a, next, r, p);
+    pass2_fetch_item<Real, PL>(vb, a, next < items ? next : item, r, p);
     pass2_item<Real, PL>(va, a, item, buf0, buf1, tw, r, p, lane, wave);
     if (next >= items) break;
     item = next + nblocks;
-    if (item < items) pass2_fetch_item<Real, PL>(va, a, item, r, p);
+    pass2_fetch_item<Real, PL>(va, a, item < items ? item : next, r, p);
     pass2_item<Real, PL>(vb, a, next, buf0, buf1, tw, r, p, lane, wave);
   }
 }
 
 template <typename Real, class PL>
-__global__ void __launch_bounds__(PL::T2) k_pass2(PassArgs a) {
+__global__ void __launch_bounds__(PL::T2)
+    __attribute__((amdgpu_waves_per_eu(PassTune<Real, PL>::waves2))) k_pass2(PassArgs a) {
   __shared__ cplx<Real> lds[PassLds<Real, PL>::X2];
   __shared__ cplx<Real> tw[PL::N2];
   init_twiddles<Real, PL::N2, PL::T2>(tw);

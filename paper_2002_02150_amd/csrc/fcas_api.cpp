@@ -338,8 +338,14 @@ int fcas_set_segment(fcas_ctx* ctx, int32_t seg_id, int64_t n_samples, const dou
   const double df = ctx->cfg.fs_hz / (double)n_samples;
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  // a re-registered segment replaces the old buffers
+  // A re-registered segment replaces the old one: its buffers are freed and
+  // the device descriptor is cleared first, so that if any later step fails
+  // the id is left unregistered (evaluations then report it as a bad
+  // segment) rather than pointing at freed memory.
   if (ctx->seg_y[seg_id]) {
+    const SegDesc empty{};
+    if ((e = hipMemcpy(ctx->d_segs + seg_id, &empty, sizeof empty, hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "segment descriptor upload");
     hipFree(ctx->seg_y[seg_id]);
     hipFree(ctx->seg_b[seg_id]);
     ctx->seg_y[seg_id] = nullptr;
@@ -439,27 +445,46 @@ hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t 
   return e;
 }
 
+// The device buffers one evaluation call works in: point descriptors,
+// per-plan work lists and their counts, pass-2 partials and the FFT
+// workspace (a context owns one set: own_bufs).
+struct EvalBufs {
+  EvalDesc* evals;
+  int32_t* lists;        // [kNumPlans][list_stride]
+  int32_t* counts;       // [kNumPlans]
+  void* part_g;          // [list_stride][part_stride]
+  int32_t* part_j;
+  void* ws;
+  size_t ws_bytes;
+  int list_stride;
+};
+
+EvalBufs own_bufs(const fcas_ctx* ctx) {
+  return EvalBufs{ctx->d_evals, ctx->d_lists, ctx->d_counts, ctx->d_part_g, ctx->d_part_j,
+                  ctx->d_ws, ctx->ws_bytes, ctx->cfg.max_batch};
+}
+
 // Enqueues the per-point set-up: descriptors and, with build_lists, the
 // per-plan work lists (their counts are zero between calls: the context starts
 // with zeros and every finalize clears them once the passes are done).
-int enqueue_setup(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, hipStream_t s,
-                  bool build_lists = true) {
+int enqueue_setup(fcas_ctx* ctx, const EvalBufs& b, int32_t n, const double* d_theta, const int32_t* d_seg,
+                  hipStream_t s, bool build_lists = true) {
   hipError_t e;
-  if ((e = launch_setup(ctx->d_net, ctx->d_segs, d_theta, d_seg, n, ctx->d_evals, ctx->d_lists, ctx->d_counts,
-                        ctx->cfg.max_batch, build_lists ? 1 : 0, ctx->d_err, s)) != hipSuccess)
+  if ((e = launch_setup(ctx->d_net, ctx->d_segs, d_theta, d_seg, n, b.evals, b.lists, b.counts, b.list_stride,
+                        build_lists ? 1 : 0, ctx->d_err, s)) != hipSuccess)
     return hip_fail(e, "set-up launch");
   return FCAS_OK;
 }
 
-PassArgs pass_args(fcas_ctx* ctx, int plan, int cap) {
+PassArgs pass_args(fcas_ctx* ctx, const EvalBufs& b, int plan, int cap) {
   PassArgs a{};
   a.segs = ctx->d_segs;
-  a.evals = ctx->d_evals;
-  a.list = ctx->d_lists + (size_t)plan * ctx->cfg.max_batch;
-  a.count = ctx->d_counts + plan;
-  a.ws = ctx->d_ws;
-  a.part_g = ctx->d_part_g;
-  a.part_j = ctx->d_part_j;
+  a.evals = b.evals;
+  a.list = b.lists + (size_t)plan * b.list_stride;
+  a.count = b.counts + plan;
+  a.ws = b.ws;
+  a.part_g = b.part_g;
+  a.part_j = b.part_j;
   a.part_stride = ctx->part_stride;
   a.n_det = ctx->net.n_det;
   a.chunk_begin = 0;
@@ -468,7 +493,7 @@ PassArgs pass_args(fcas_ctx* ctx, int plan, int cap) {
 }
 
 // One persistent launch of the fused schedule for the points of `plan`.
-int enqueue_fused(fcas_ctx* ctx, int plan, int n, int cap, hipStream_t s) {
+int enqueue_fused(fcas_ctx* ctx, const EvalBufs& b, int plan, int n, int cap, hipStream_t s) {
   const PlanInfo& pi = kPlans[plan];
   if (ctx->fused_cap[plan] == 0) {
     const int nb = fused_blocks_per_cu(plan);
@@ -485,7 +510,7 @@ int enqueue_fused(fcas_ctx* ctx, int plan, int n, int cap, hipStream_t s) {
     lag = slots - 1;
   }
   FusedArgs f{};
-  f.p = pass_args(ctx, plan, cap);
+  f.p = pass_args(ctx, b, plan, cap);
   f.done1 = ctx->d_done + (size_t)plan * 2 * ctx->cfg.max_batch;
   f.done2 = f.done1 + ctx->cfg.max_batch;
   f.err = ctx->d_err;
@@ -506,45 +531,76 @@ int enqueue_fused(fcas_ctx* ctx, int plan, int n, int cap, hipStream_t s) {
   return e == hipSuccess ? FCAS_OK : hip_fail(e, "fused launch");
 }
 
-// Enqueues set-up, the FFT passes of every plan in use, and finalize.  Plans
-// with a middle pass, or with passes of unequal work items, always run as
-// separate launches (the fused schedule covers the other two-pass plans).
+int enqueue_passes(fcas_ctx* ctx, const EvalBufs& b, int32_t n, double* d_fitness, int32_t* d_argmax,
+                   hipStream_t s, bool fused_ok, bool timed);
+
+// Enqueues set-up, the FFT passes of every plan in use, and finalize.
+int enqueue_eval(fcas_ctx* ctx, const EvalBufs& b, int32_t n, const double* d_theta, const int32_t* d_seg,
+                 double* d_fitness, int32_t* d_argmax, hipStream_t s, bool fused_ok = true, bool timed = true) {
+  int rc = enqueue_setup(ctx, b, n, d_theta, d_seg, s);
+  if (rc) return rc;
+  if ((rc = enqueue_passes(ctx, b, n, d_fitness, d_argmax, s, fused_ok, timed))) {
+    // the set-up appended to the work lists and only finalize clears their
+    // counts: clear them here so that the next call starts from empty lists
+    launch_zero_i32(b.counts, kNumPlans, s);
+  }
+  return rc;
+}
+
 int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,
                  int32_t* d_argmax, hipStream_t s) {
+  return enqueue_eval(ctx, own_bufs(ctx), n, d_theta, d_seg, d_fitness, d_argmax, s);
+}
+
+// The FFT passes of every plan in use, then finalize (which clears the
+// work-list counts).  Plans with a middle pass, or with passes of unequal work
+// items, always run as separate launches (the fused schedule covers the other
+// two-pass plans, when fused_ok).  With `timed` false no timing events are
+// recorded whatever the context's setting.
+int enqueue_passes(fcas_ctx* ctx, const EvalBufs& b, int32_t n, double* d_fitness, int32_t* d_argmax,
+                   hipStream_t s, bool fused_ok, bool timed) {
   hipError_t e;
-  int rc = enqueue_setup(ctx, n, d_theta, d_seg, s);
-  if (rc) return rc;
-  if (ctx->schedule == FCAS_SCHEDULE_FUSED &&
-      (e = launch_zero_i32(ctx->d_done, 2 * kNumPlans * ctx->cfg.max_batch, s)) != hipSuccess)
+  int rc;
+  const bool fused = fused_ok && ctx->schedule == FCAS_SCHEDULE_FUSED;
+  if (fused && (e = launch_zero_i32(ctx->d_done, 2 * kNumPlans * ctx->cfg.max_batch, s)) != hipSuccess)
     return hip_fail(e, "zero tile counters");
+  const bool was_timing = ctx->timing;
+  ctx->timing = was_timing && timed;
   for (int plan = 0; plan < kNumPlans; ++plan) {
     if (ctx->plan_refs[plan] <= 0) continue;
     const PlanInfo& pi = kPlans[plan];
     const size_t slot_bytes = 2 * (size_t)pi.n * ctx->elt;
-    int cap = (int)std::min<size_t>(ctx->ws_bytes / slot_bytes, (size_t)n);
+    int cap = (int)std::min<size_t>(b.ws_bytes / slot_bytes, (size_t)n);
     if (cap < 1) cap = 1;
-    if (ctx->schedule == FCAS_SCHEDULE_FUSED && pi.nm == 1 && pi.threads1[0] == pi.threads2[0]) {
-      if ((rc = enqueue_fused(ctx, plan, n, cap, s))) return rc;
+    if (fused && pi.nm == 1 && pi.threads1[0] == pi.threads2[0]) {
+      if ((rc = enqueue_fused(ctx, b, plan, n, cap, s))) {
+        ctx->timing = was_timing;
+        return rc;
+      }
       continue;
     }
-    PassArgs a = pass_args(ctx, plan, cap);
+    PassArgs a = pass_args(ctx, b, plan, cap);
     for (int begin = 0; begin < n; begin += cap) {
       a.chunk_begin = begin;
       const int m = std::min(cap, n - begin);
       const int g1 = std::min(m * pi.tiles1[ctx->prec], ctx->grid1[plan]);
       const int g2 = std::min(m * pi.tiles2[ctx->prec], ctx->grid2[plan]);
-      if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) return hip_fail(e, "pass-1 launch");
-      if (pi.nm > 1) {
+      const char* what = nullptr;
+      if ((e = timed_launch(ctx, ctx->t_pass1, s, 1, plan, a, g1)) != hipSuccess) what = "pass-1 launch";
+      if (!what && pi.nm > 1) {
         const int gm = std::min(m * pi.tilesm[ctx->prec] * (2 / kPassmSeries), ctx->grid2[plan]);
-        if ((e = timed_launch(ctx, ctx->t_passm, s, 3, plan, a, gm)) != hipSuccess)
-          return hip_fail(e, "middle-pass launch");
+        if ((e = timed_launch(ctx, ctx->t_passm, s, 3, plan, a, gm)) != hipSuccess) what = "middle-pass launch";
       }
-      if ((e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) return hip_fail(e, "pass-2 launch");
+      if (!what && (e = timed_launch(ctx, ctx->t_pass2, s, 2, plan, a, g2)) != hipSuccess) what = "pass-2 launch";
+      if (what) {
+        ctx->timing = was_timing;
+        return hip_fail(e, what);
+      }
     }
   }
-  if ((e = launch_finalize(ctx->prec, ctx->d_evals, ctx->d_segs, ctx->d_part_g, ctx->d_part_j, n, ctx->part_stride,
-                           ctx->d_plan_parts2, ctx->d_counts, ctx->d_evaluated, d_fitness, d_argmax, s)) !=
-      hipSuccess)
+  ctx->timing = was_timing;
+  if ((e = launch_finalize(ctx->prec, b.evals, ctx->d_segs, b.part_g, b.part_j, n, ctx->part_stride,
+                           ctx->d_plan_parts2, b.counts, ctx->d_evaluated, d_fitness, d_argmax, s)) != hipSuccess)
     return hip_fail(e, "finalize launch");
   return FCAS_OK;
 }
@@ -593,7 +649,7 @@ int fitness_polish(fcas_ctx* ctx, int32_t n, double* d_theta, const int32_t* d_s
   if ((rc = enqueue_eval(ctx, n, d_theta, d_seg, d_fitness, d_argmax, s))) return rc;
   for (int step = 0; step < n_steps; ++step) {
     // descriptors of the current points (their maximising samples are already in d_argmax)
-    if (step > 0 && (rc = enqueue_setup(ctx, n, d_theta, d_seg, s, false))) return rc;
+    if (step > 0 && (rc = enqueue_setup(ctx, own_bufs(ctx), n, d_theta, d_seg, s, false))) return rc;
     if ((e = launch_gradient(ctx->prec, ctx->grad, ctx->d_net, ctx->d_segs, ctx->d_evals, d_theta, d_argmax, n,
                              ctx->net.n_det, ctx->d_pol_grad, s)) !=
             hipSuccess ||
@@ -787,8 +843,26 @@ int pso_best(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, d
   if (rc) return rc;
   if (!d_out_f || !d_out_theta || !d_out_j || !d_out_run) return fail(FCAS_EINVAL, "NULL device pointer");
   hipSetDevice(ctx->device);
-  hipError_t e = launch_pso_best(d, d_out_f, d_out_theta, d_out_j, d_out_run, (hipStream_t)hip_stream);
+  hipError_t e =
+      launch_pso_best(d, d.n_runs, d.n_runs, d_out_f, d_out_theta, d_out_j, d_out_run, (hipStream_t)hip_stream);
   return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_best launch");
+}
+
+int pso_best_segments(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, int32_t runs_per_segment,
+                      int32_t runs_used, double* d_out_f, double* d_out_theta, int32_t* d_out_j, int32_t* d_out_run,
+                      void* hip_stream) {
+  PsoDev d{};
+  int rc = make_pso(ctx, p, s, &d);
+  if (rc) return rc;
+  if (runs_per_segment < 1 || d.n_runs % runs_per_segment != 0)
+    return fail(FCAS_EINVAL, "runs_per_segment = %d must divide n_runs = %d", runs_per_segment, d.n_runs);
+  if (runs_used < 1 || runs_used > runs_per_segment)
+    return fail(FCAS_EINVAL, "runs_used = %d must be in [1, runs_per_segment = %d]", runs_used, runs_per_segment);
+  if (!d_out_f || !d_out_theta || !d_out_j || !d_out_run) return fail(FCAS_EINVAL, "NULL device pointer");
+  hipSetDevice(ctx->device);
+  hipError_t e = launch_pso_best(d, runs_per_segment, runs_used, d_out_f, d_out_theta, d_out_j, d_out_run,
+                                 (hipStream_t)hip_stream);
+  return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_best_segments launch");
 }
 
 }  // extern "C"

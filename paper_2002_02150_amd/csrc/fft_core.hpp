@@ -17,7 +17,32 @@
 #define FCAS_HD inline
 #endif
 
+// Address spaces of the device build.  Tables that a kernel only reads, and
+// that earlier launches wrote, are read through the constant address space:
+// with a uniform address the compiler then issues scalar loads, which are
+// counted apart from the vector memory operations, so that reading the next
+// work item's descriptors never waits for the stores and prefetches in flight.
+// Segment data reached through pointers held in those tables are read through
+// the global address space (vector loads rather than flat ones).  The host
+// build (CPU emulator) reads plain memory.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define FCAS_AS_CONST __attribute__((address_space(4)))
+#define FCAS_AS_GLOBAL __attribute__((address_space(1)))
+#else
+#define FCAS_AS_CONST
+#define FCAS_AS_GLOBAL
+#endif
+
 namespace fcas {
+
+template <class T>
+FCAS_HD const FCAS_AS_CONST T* const_view(const T* p) {
+  return (const FCAS_AS_CONST T*)p;
+}
+template <class T>
+FCAS_HD const FCAS_AS_GLOBAL T* global_view(const T* p) {
+  return (const FCAS_AS_GLOBAL T*)p;
+}
 
 template <typename R>
 struct cplx {

@@ -370,21 +370,58 @@ FCAS_HD void pass1_fetch(Pass1Data<Real, PL, DT>& d, const SegDesc& sg, int tile
   static_assert(DT > 0, "prefetch needs a compile-time detector count");
   const int k2 = tile * PL::C + c;
   d.k0 = p * PL::W1 + k2;
-  const cplx<Real>* y = (const cplx<Real>*)sg.y;
+  const FCAS_AS_GLOBAL cplx<Real>* y = global_view((const cplx<Real>*)sg.y);
+  const FCAS_AS_GLOBAL double* bt = global_view(sg.b);
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
     const int k = d.k0 + q * DK;
     d.in[q] = (k >= sg.k_lo) && (k <= sg.k_hi);
     const int kk = d.in[q] ? k - sg.k_lo : 0;
-    d.b[q] = sg.b[kk];
+    d.b[q] = bt[kk];
 #pragma unroll
     for (int i = 0; i < DT; ++i) d.y[i][q] = y[(int64_t)kk * DT + i];
   }
 }
 
-// exp(2 pi i Phi) for an in-band bin with basis value b, 0 otherwise.
-template <typename Real>
-FCAS_HD cplx<Real> band_phase(const EvalDesc& ev, double b, bool in) {
+// What the pass-1 arithmetic reads of a point's descriptor, in the working
+// precision: phase coefficients, delay ramps, basis Q and ramp steps of the
+// DT detectors.  `ev` points to an EvalDesc (through the constant address
+// space in the kernels, so that these uniform values are scalar loads held in
+// scalar registers).
+template <typename Real, int DT>
+struct Pass1Point {
+  double coef[4];
+  double dly[DT];
+  Real q[DT][2];
+  Real step[DT][2];
+};
+
+template <typename Real, int DT, class P>
+FCAS_HD Pass1Point<Real, DT> pass1_point(P ev) {
+  Pass1Point<Real, DT> r;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) r.coef[k] = ev->coef[k];
+#pragma unroll
+  for (int i = 0; i < DT; ++i) {
+    r.dly[i] = ev->dly[i];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      if constexpr (sizeof(Real) == 4) {
+        r.q[i][m] = ev->qf[i][m];
+        r.step[i][m] = ev->step1f[i][m];
+      } else {
+        r.q[i][m] = ev->q[i][m];
+        r.step[i][m] = ev->step1[i][m];
+      }
+    }
+  }
+  return r;
+}
+
+// exp(2 pi i Phi) for an in-band bin with basis value b, 0 otherwise (Ev: a
+// descriptor with the phase coefficients `coef`).
+template <typename Real, class Ev>
+FCAS_HD cplx<Real> band_phase(const Ev& ev, double b, bool in) {
   const double ph = common_phase(ev.coef, b);
   Real s, cc;
   sincos_rev((Real)(ph - rint(ph)), &s, &cc);
@@ -392,8 +429,8 @@ FCAS_HD cplx<Real> band_phase(const EvalDesc& ev, double b, bool in) {
 }
 
 // Delay ramp of detector i at the thread's first bin k0 (FP64 reduction).
-template <typename Real>
-FCAS_HD cplx<Real> first_ramp(const EvalDesc& ev, int i, int k0) {
+template <typename Real, class Ev>
+FCAS_HD cplx<Real> first_ramp(const Ev& ev, int i, int k0) {
   const double ph0 = (double)k0 * ev.dly[i];
   Real s, cc;
   sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
@@ -402,7 +439,8 @@ FCAS_HD cplx<Real> first_ramp(const EvalDesc& ev, int i, int k0) {
 
 // The prologue arithmetic on prefetched data (same results as pass1_prologue).
 template <typename Real, class PL, int DT>
-FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL, DT>& d, const EvalDesc& ev) {
+FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL, DT>& d,
+                           const Pass1Point<Real, DT>& ev) {
   constexpr int QH = PL::E1 / 2;
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
@@ -412,8 +450,8 @@ FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL,
 #pragma unroll
   for (int i = 0; i < DT; ++i) {
     cplx<Real> ramp = first_ramp<Real>(ev, i, d.k0);
-    const cplx<Real> step = ramp_step<Real>(ev, i);
-    const Real q0 = Basis<Real>::get(ev, i, 0), q1 = Basis<Real>::get(ev, i, 1);
+    const cplx<Real> step = mk<Real>(ev.step[i][0], ev.step[i][1]);
+    const Real q0 = ev.q[i][0], q1 = ev.q[i][1];
 #pragma unroll
     for (int q = 0; q < QH; ++q) {
       const cplx<Real> u = mul(d.y[i][q], ramp);

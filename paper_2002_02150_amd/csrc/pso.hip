@@ -137,16 +137,22 @@ __global__ void k_pso_step(PsoDev p, const double* __restrict__ fitness, const i
   }
 }
 
-__global__ void k_pso_best(PsoDev p, double* out_f, double* out_theta, int32_t* out_j, int32_t* out_run) {
+// Best of the first u runs of each group of m consecutive runs (one group per
+// searched segment; m = u = n_runs: the whole swarm): the largest run best,
+// lowest run index on ties, mapped from unit-cube to rectangle coordinates.
+// One thread per group.
+__global__ void k_pso_best(PsoDev p, int m, int u, double* out_f, double* out_theta, int32_t* out_j,
+                           int32_t* out_run) {
 #pragma clang fp contract(off)
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int b = 0;
-  for (int r = 1; r < p.n_runs; ++r)
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= p.n_runs / m) return;
+  int b = g * m;
+  for (int r = b + 1; r < g * m + u; ++r)
     if (p.best_f[r] > p.best_f[b]) b = r;
-  out_f[0] = p.best_f[b];
-  out_j[0] = p.best_j[b];
-  out_run[0] = b;
-  for (int d = 0; d < 4; ++d) out_theta[d] = p.lo[d] + p.best_x[4 * b + d] * p.span[d];
+  out_f[g] = p.best_f[b];
+  out_j[g] = p.best_j[b];
+  out_run[g] = b;
+  for (int d = 0; d < 4; ++d) out_theta[4 * g + d] = p.lo[d] + p.best_x[4 * b + d] * p.span[d];
 }
 
 static int block_for(int P) { return ((P + 63) / 64) * 64; }
@@ -163,9 +169,11 @@ hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_pso_best(const PsoDev& p, double* out_f, double* out_theta, int32_t* out_j, int32_t* out_run,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_pso_best, dim3(1), dim3(64), 0, s, p, out_f, out_theta, out_j, out_run);
+hipError_t launch_pso_best(const PsoDev& p, int runs_per_group, int runs_used, double* out_f, double* out_theta,
+                           int32_t* out_j, int32_t* out_run, hipStream_t s) {
+  const int groups = p.n_runs / runs_per_group;
+  hipLaunchKernelGGL(k_pso_best, dim3((groups + 63) / 64), dim3(64), 0, s, p, runs_per_group, runs_used, out_f,
+                     out_theta, out_j, out_run);
   return hipGetLastError();
 }
 

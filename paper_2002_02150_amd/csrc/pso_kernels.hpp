@@ -25,7 +25,7 @@ struct PsoDev {
 hipError_t launch_pso_init(const PsoDev& p, double* theta_out, hipStream_t s);
 hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, double* theta_next,
                            hipStream_t s);
-hipError_t launch_pso_best(const PsoDev& p, double* out_f, double* out_theta, int32_t* out_j, int32_t* out_run,
-                           hipStream_t s);
+hipError_t launch_pso_best(const PsoDev& p, int runs_per_group, int runs_used, double* out_f, double* out_theta,
+                           int32_t* out_j, int32_t* out_run, hipStream_t s);
 
 }  // namespace fcas

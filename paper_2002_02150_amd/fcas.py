@@ -27,7 +27,8 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP",
 
 EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_plan_count",
             "fcas_plan_info", "fcas_select_plan", "fcas_set_segment", "fcas_set_segment_range",
-            "fitness_eval_batch", "fitness_grad_batch", "fitness_polish", "pso_init", "pso_step", "pso_best",
+            "fitness_eval_batch", "fitness_grad_batch", "fitness_polish", "pso_init",
+            "pso_step", "pso_best", "pso_best_segments",
             "fcas_inject", "fcas_evaluated", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
 
 
@@ -90,6 +91,8 @@ def library():
         "pso_init": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp], ctypes.c_int),
         "pso_step": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, vp, vp], ctypes.c_int),
         "pso_best": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, vp, vp, vp], ctypes.c_int),
+        "pso_best_segments": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), i32, i32, vp, vp, vp, vp,
+                               vp], ctypes.c_int),
         "fcas_inject": ([vp, i64, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp, vp], ctypes.c_int),
         "fcas_evaluated": ([vp, ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
         "fcas_device_error": ([vp, ctypes.POINTER(i32)], ctypes.c_int),
@@ -349,6 +352,22 @@ class Swarm:
         _check(library().pso_step(self.ctx._h, ctypes.byref(self._p), ctypes.byref(self._s), _ptr(fitness),
                                   _ptr(argmax), _ptr(self.theta), _stream(self.ctx.device)))
         return self.theta
+
+    def best_segments(self, runs_per_segment, runs_used=None):
+        """pso_best_segments: per segment g (runs g*m .. g*m + m - 1, m =
+        runs_per_segment) the best of its first runs_used runs (default all):
+        fitness, theta, coalescence sample and run index, as device tensors
+        [n_seg], [n_seg, 4], [n_seg], [n_seg]."""
+        m = int(runs_per_segment)
+        u = m if runs_used is None else int(runs_used)
+        g, dev = max(self.cfg.n_runs // max(m, 1), 1), self.ctx.device
+        f = torch.empty(g, dtype=torch.float64, device=dev)
+        th = torch.empty(g, 4, dtype=torch.float64, device=dev)
+        j = torch.empty(g, dtype=torch.int32, device=dev)
+        run = torch.empty(g, dtype=torch.int32, device=dev)
+        _check(library().pso_best_segments(self.ctx._h, ctypes.byref(self._p), ctypes.byref(self._s), m, u,
+                                           _ptr(f), _ptr(th), _ptr(j), _ptr(run), _stream(dev)))
+        return f, th, j, run
 
     def best(self):
         _check(library().pso_best(self.ctx._h, ctypes.byref(self._p), ctypes.byref(self._s), _ptr(self.out_f),

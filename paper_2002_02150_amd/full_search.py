@@ -9,10 +9,12 @@ Data: a seeded Gaussian time series per detector (H, L, V, K) at 2048 Hz with
 the analytic PSD above 20 Hz, cut into overlapping 128-s segments (262144
 samples) at a common stride; 8 double-neutron-star injections (component
 masses U[1.2, 1.6] Msun, isotropic sky and orientation, network SNR U[10, 12],
-coalescence uniform over the hour).  Each injection is added, as the SPA
-response of fcas_inject, to the Fourier data of every segment whose window
-holds its coalescence (a chirp that began before the window wraps around in
-that segment's data, as the FFT of the search assumes anyway).
+coalescence uniform over the hour from 128 s on, so that every chirp starts
+inside the data).  Each injection is synthesised once over the whole stretch
+(fcas_inject on the Fourier grid of the full length, network SNR over the
+stretch), brought to the time domain and added to the noise series before the
+segments are cut, so that every segment overlapping a chirp holds the part of
+it its window sees.
 
 Search: every segment gets 8 independent PSO runs of 40 particles and 2000
 iterations; all segments' runs are one batch of 17,920 points per iteration,
@@ -63,7 +65,25 @@ def layout(total: int, n_seg: int, seg: int = SEG):
     return starts, stride, ranges
 
 
-def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, log=print):
+def add_injections(ctx, series, injections, dev):
+    """Adds each injection to the time series (D x total, in place): its SPA
+    response on the Fourier grid of the whole stretch (fcas_inject, scaled to
+    its network SNR over the stretch), brought to the time domain (continuum
+    units: x = fs * irfft)."""
+    import synth
+    D, total = series.shape
+    psd_full = torch.from_numpy(synth.psd_matrix(D, total, FS)).to(dev)
+    for inj in injections:
+        hf = torch.zeros(D, total // 2 + 1, dtype=torch.complex128, device=dev)
+        ctx.inject(hf, psd_full, inj["alpha"], inj["delta"], inj["tau0"], inj["tau15"], inj["psi"], inj["phi_c"],
+                   inj["cos_iota"], inj["tc_sample"] / FS, inj["snr"])
+        series += FS * np.fft.irfft(hf.cpu().numpy(), n=total, axis=1)
+        del hf
+
+
+def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, keep_data=False, log=print):
+    """The search of the stretch; keep_data also returns every segment's
+    Fourier data (host copies; the PSD is synth.psd_matrix) and results."""
     import synth
     dev = torch.device("cuda", 0)
     total = int(round(minutes * 60.0 * FS))
@@ -72,6 +92,9 @@ def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, lo
     D = net.n_det
     lo_box, hi_box = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
 
+    n = n_seg * RUNS * PARTICLES
+    ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo_box, box_hi=hi_box, max_batch=n,
+                               max_segments=n_seg, max_samples=SEG)
     t0 = time.perf_counter()
     series = np.stack([synth.td_noise(np.random.default_rng(synth.seed_sequence(seed, 0, i)), total, FS)
                        for i in range(D)])
@@ -79,24 +102,21 @@ def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, lo
     injections = []
     for _ in range(n_inj):
         inj = synth.draw_injection(rng, total, m_lo=1.2, m_hi=1.6)
-        inj["tc_sample"] = int(rng.integers(SEG // 2, total - SEG // 4))
+        inj["tc_sample"] = int(rng.integers(SEG, total - SEG // 4))
         inj["snr"] = float(rng.uniform(10.0, 12.0))
         inj["tau0"], inj["tau15"] = chirp_times(inj["m1"], inj["m2"], F_LOW)
         injections.append(inj)
+    add_injections(ctx, series, injections, dev)
     t_series = time.perf_counter() - t0
 
-    n = n_seg * RUNS * PARTICLES
-    ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo_box, box_hi=hi_box, max_batch=n,
-                               max_segments=n_seg, max_samples=SEG)
     psd = torch.from_numpy(synth.psd_matrix(D, SEG, FS)).to(dev)
     t1 = time.perf_counter()
+    kept = []
     for s, a in enumerate(starts):
-        xf = torch.from_numpy(np.stack([synth.segment_fd(series[i], a, SEG, FS) for i in range(D)])).to(dev)
-        for inj in injections:
-            if a <= inj["tc_sample"] < a + SEG:
-                ctx.inject(xf, psd, inj["alpha"], inj["delta"], inj["tau0"], inj["tau15"], inj["psi"],
-                           inj["phi_c"], inj["cos_iota"], (inj["tc_sample"] - a) / FS, inj["snr"])
-        ctx.set_segment(s, xf, psd)
+        xf_np = np.stack([synth.segment_fd(series[i], a, SEG, FS) for i in range(D)])
+        if keep_data:
+            kept.append(xf_np)
+        ctx.set_segment(s, torch.from_numpy(xf_np).to(dev), psd)
         ctx.set_segment_range(s, *ranges[s])
     torch.cuda.synchronize()
     t_prep = time.perf_counter() - t1
@@ -116,6 +136,8 @@ def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, lo
                            device=dev)
         rho0_sq = ctx.eval(th0, torch.tensor([s], dtype=torch.int32, device=dev))[0].item()
         found.append(dict(segment=s, snr=inj["snr"], m1=inj["m1"], m2=inj["m2"], rho0_sq=rho0_sq,
+                          tc_sample=inj["tc_sample"],
+                          theta0=[inj["alpha"], inj["delta"], inj["tau0"], inj["tau15"]],
                           rho_sq_pso=float(f_pso[s]), rho_sq=float(f_pol[s]),
                           dt_c_samples=int(starts[s] + j_pol[s] - inj["tc_sample"]),
                           d_tau0=float(theta[s, 2] - inj["tau0"]), d_tau15=float(theta[s, 3] - inj["tau15"])))
@@ -126,13 +148,17 @@ def run(minutes=60.0, n_seg=56, iters=2000, n_inj=8, seed=5, polish_steps=20, lo
     noise_only = [float(f_pol[s]) for s in range(n_seg) if s not in with_inj]
     ctx.close()
     T = total / FS
-    return dict(data_seconds=T, segments=n_seg, stride_samples=stride, iterations=iters,
-                points_per_iteration=n, evaluated_points=evaluated, t_run_s=t_run, t_run_over_t=t_run / T,
-                evaluated_points_per_s=evaluated / t_run,
-                data_generation_s=t_series, segment_preparation_s=t_prep, polish_improved_segments=improved,
-                injections=found, noise_only_max_rho_sq=dict(
-                    median=float(np.median(noise_only)) if noise_only else None,
-                    max=float(np.max(noise_only)) if noise_only else None))
+    out = dict(data_seconds=T, segments=n_seg, stride_samples=stride, iterations=iters,
+               points_per_iteration=n, evaluated_points=evaluated, t_run_s=t_run, t_run_over_t=t_run / T,
+               evaluated_points_per_s=evaluated / t_run,
+               data_generation_s=t_series, segment_preparation_s=t_prep, polish_improved_segments=improved,
+               injections=found, noise_only_max_rho_sq=dict(
+                   median=float(np.median(noise_only)) if noise_only else None,
+                   max=float(np.max(noise_only)) if noise_only else None))
+    if keep_data:
+        out["segment_data"] = dict(xf=kept, starts=starts, ranges=ranges, theta=theta, rho_sq=f_pol,
+                                   rho_sq_pso=f_pso, argmax=j_pol)
+    return out
 
 
 def run_single_segment(minutes=60.0, iters=1000, runs=RUNS, seed=7, snr=(10.0, 12.0), polish_steps=20, log=print):

@@ -216,3 +216,24 @@ def segment_fd(x, start: int, n_samples: int, fs: float):
     """One-sided Fourier data (continuum units, dt times the DFT) of the
     rectangular window x[start : start + n_samples]."""
     return np.fft.rfft(x[start:start + n_samples]) / fs
+
+
+# Source locations of the paper's simulated signals (Sec. V): sky position in
+# degrees (alpha, delta) and the polarisation angle psi in degrees; both use
+# equal component masses of 1.5 Msun.  L4 and L5 are the best and the worst
+# conditioned antenna-pattern matrices of the HLVK network among the
+# locations of the earlier work the paper draws them from.
+PAPER_SOURCES = {"L4": (32.09, -53.86), "L5": (150.11, -60.16)}
+PAPER_PSI_DEG = 30.0
+PAPER_MASSES = (1.5, 1.5)
+
+
+def paper_source(name: str, rng: np.random.Generator, tc_sample: int):
+    """An injection at the paper's location `name` (L4 or L5), psi = 30 deg,
+    1.5 + 1.5 Msun; the paper leaves the coalescence phase and the inclination
+    unstated, so they are drawn uniformly (phi_c in [0, 2 pi), cos iota in
+    [-1, 1])."""
+    a, d = PAPER_SOURCES[name]
+    return dict(m1=PAPER_MASSES[0], m2=PAPER_MASSES[1], alpha=math.radians(a), delta=math.radians(d),
+                psi=math.radians(PAPER_PSI_DEG), phi_c=float(rng.uniform(0.0, 2.0 * math.pi)),
+                cos_iota=float(rng.uniform(-1.0, 1.0)), tc_sample=int(tc_sample))

@@ -64,7 +64,7 @@ static void prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, const SegDe
   if constexpr (DT > 0) {
     Pass1Data<Real, PL, DT> d;
     pass1_fetch<Real, PL, DT>(d, sg, tile, c, p);
-    pass1_compute<Real, PL, DT>(v, d, ev);
+    pass1_compute<Real, PL, DT>(v, d, pass1_point<Real, DT>(&ev));
   } else {
     pass1_prologue<Real, PL, 0>(v, ev, sg, n_det, tile, c, p);
   }

@@ -13,10 +13,12 @@ from tests._gpu import dev, make_ctx, require_gpu, upload
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 2e-4), (1, 1e-8)], ids=["mixed", "fp64"])
-def test_gradient_matches_oracle(prec, tol):
+@pytest.mark.parametrize("prec,tol,rtol", [(0, 2e-4, 1e-2), (1, 1e-8, 1e-7)], ids=["mixed", "fp64"])
+def test_gradient_matches_oracle(prec, tol, rtol):
     """dGamma^2/dtheta at the GPU's maximising sample vs the oracle's analytic
-    gradient at the same sample (itself pinned to finite differences)."""
+    gradient at the same sample (itself pinned to finite differences): every
+    component within tol of the gradient's scale in rectangle-width units, and
+    every component above 1e-3 of that scale within rtol of itself."""
     require_gpu()
     case = Case("HLVK", 16384, 2048.0, snr=12.0, cfg=20)
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
@@ -32,6 +34,8 @@ def test_gradient_matches_oracle(prec, tol):
         scale = np.max(np.abs(go * w))     # gradient scale in box-width units
         err = np.abs((g[k] - go) * w)
         assert np.all(err <= tol * scale), (k, g[k], go)
+        big = np.abs(go * w) > 1e-3 * scale
+        assert np.all(err[big] <= rtol * np.abs(go * w)[big]), (k, g[k], go)
     ctx.close()
 
 
@@ -55,8 +59,20 @@ def test_fitnessfn_backward_and_polish():
     # the polished points are what they claim: re-evaluate them
     f3, j3 = ctx.eval(th2, seg)
     assert torch.equal(f3, f2) and torch.equal(j3, j2)
-    # and they approach the truth's fitness from below-or-above consistently
-    assert torch.all(f2 > f.detach()) or torch.all(f2 >= f.detach())
+    ctx.close()
+    # On noiseless data the global maximum is SNR^2 at the true parameters:
+    # the polish must raise every point strictly, never pass SNR^2, and close
+    # most of the gap to it.
+    clean = Case("HLVK", 16384, 2048.0, snr=15.0, noise=False, cfg=22)
+    ctx = make_ctx(clean, 0, max_batch=32)
+    upload(ctx, 0, clean)
+    th = torch.from_numpy(synth.near_point(rng, 4, clean.theta0, lo, hi, 0.002)).to(dev())
+    fs, _ = ctx.eval(th, seg)
+    fs = fs.clone()
+    _, fp, _ = polish(ctx, th.clone(), seg, steps=10)
+    assert torch.all(fp > fs), (fs, fp)
+    assert torch.all(fp <= 225.0 * (1 + 1e-4)), fp
+    assert (225.0 - fp).sum() < 0.5 * (225.0 - fs).sum(), (fs, fp)
     ctx.close()
 
 
@@ -96,6 +112,49 @@ def test_pso_trajectory_bitwise_equal_to_oracle():
     bf, bt, bj, br = sw.best()
     of, ot, oj, orun = OP.best_of_runs(st, lo, hi)
     assert bf.item() == of and np.array_equal(bt.cpu().numpy(), ot) and bj.item() == oj and br.item() == orun
+    ctx.close()
+
+
+def test_pso_best_segments_bitwise_equal_to_oracle():
+    """Best of the runs of each segment (runs grouped by segment, the layout of
+    the multi-segment searches; optionally of only the first runs of each
+    group, as the tuning metric compares), on the device, equals the oracle's
+    best of runs applied to each group bit for bit: fitness, theta, sample and
+    run index (lowest run on ties, which the fitness values force here)."""
+    require_gpu()
+    from types import SimpleNamespace
+    from paper_2002_02150_amd import PsoConfig, Swarm
+    case = Case("HL", 2048, 1024.0, snr=None, cfg=24)
+    ctx = make_ctx(case, 0, max_batch=240)
+    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    R, P, m = 6, 40, 2
+    cfg = PsoConfig(n_runs=R, n_particles=P, n_iter=4, seed=99)
+    sw = Swarm(ctx, cfg)
+    sw.init()
+    p = OP.PsoParams(n_runs=R, n_particles=P, n_iter=4, seed=cfg.seed)
+    st, _ = OP.init(p, lo, hi)
+    rng = np.random.default_rng(12)
+    for it in range(4):
+        fit = rng.normal(50.0, 10.0, R * P)
+        fit[rng.random(R * P) < 0.2] = -np.inf
+        fit[P:2 * P] = fit[:P]          # runs 0 and 1 (segment 0) tie
+        am = rng.integers(0, 2048, R * P).astype(np.int32)
+        sw.step(torch.from_numpy(fit).to(dev()), torch.from_numpy(am).to(dev()))
+        OP.step(p, st, fit, am, it, lo, hi)
+    for m, u in ((2, 2), (3, 2), (6, 4), (1, 1)):
+        f, th, j, run = (t.cpu().numpy() for t in sw.best_segments(m, u))
+        assert len(f) == R // m
+        for g in range(R // m):
+            sl = slice(g * m, g * m + u)
+            sub = SimpleNamespace(best_f=st.best_f[sl], best_x=st.best_x[sl], best_j=st.best_j[sl])
+            of, ot, oj, orun = OP.best_of_runs(sub, lo, hi)
+            assert f[g] == of and np.array_equal(th[g], ot) and j[g] == oj and run[g] == g * m + orun, (m, u, g)
+        if m == 2:
+            assert run[0] == 0
+    from paper_2002_02150_amd import FcasError
+    for m, u in ((4, 4), (2, 3), (2, 0)):      # m must divide the 6 runs, 1 <= u <= m
+        with pytest.raises(FcasError):
+            sw.best_segments(m, u)
     ctx.close()
 
 
@@ -150,24 +209,6 @@ def test_pso_search_recovers_injection():
     ctx.close()
 
 
-def test_full_search_small():
-    """The full-length search (segments cut from one time series, per-segment
-    coalescence ranges that tile the data, one batched swarm over all
-    segments, polish of each segment's best) runs end to end at a small size;
-    the polish never lowers a segment's best fitness, and every reported
-    injection lies in the searched range of its segment."""
-    require_gpu()
-    from paper_2002_02150_amd.full_search import layout, run
-    out = run(minutes=4.0, n_seg=3, iters=30, n_inj=1, polish_steps=3, log=lambda s: None)
-    assert out["segments"] == 3 and out["iterations"] == 30
-    assert out["t_run_s"] > 0 and out["evaluated_points"] > 0
-    starts, stride, ranges = layout(int(4 * 60 * 2048), 3)
-    assert stride == out["stride_samples"]
-    for d in out["injections"]:
-        assert d["rho_sq"] >= d["rho_sq_pso"] - 1e-9
-        assert d["rho0_sq"] > 0
-
-
 def test_single_segment_search_small():
     """The paper's layout (the whole stretch one segment, three-pass FFT plan,
     one injection, batched runs, polish) end to end on a 225-s stretch."""
@@ -191,26 +232,3 @@ def test_hour_h0_small():
     assert sorted(out["rho"]) == [1, 2] and all(v > 0 for v in out["rho"].values())
     c = combine([out])
     assert c["segments_h0"] == 2 and c["eta"] > max(out["rho"].values())
-
-
-def test_hour_h1_small():
-    """The hour-long H1 mode (an injection in an hour of noise, three-pass FFT,
-    rho' and rho0) runs end to end for one segment."""
-    require_gpu()
-    from paper_2002_02150_amd.detection import hour_h1
-    out = hour_h1(12.0, 0, 0, iters=6, runs=1, polish_steps=1, log=lambda s: None)
-    v = out["values"][0]
-    assert v["rho"] > 0 and v["rho0"] > 0 and out["snr"] == 12.0
-
-
-def test_detection_study_small():
-    """The detection-statistics study (time-slid noise-only segments, injected
-    segments, one batched search, lognormal threshold, detection probability
-    and loss) runs end to end at a small size with consistent outputs."""
-    require_gpu()
-    from paper_2002_02150_amd.detection import run
-    out = run(slides=1, per_snr=2, snrs=(12.0,), iters=20, n_per_slide=4, log=lambda s: None)
-    assert out["segments_h0"] == 4 and out["segments_h1"] == 2
-    assert out["eta"] > out["h0_rho_quantiles"][0.5] > 0
-    row = out["table"][0]
-    assert 0.0 <= row["detection_probability"] <= 1.0 and row["median_rho0"] > 0

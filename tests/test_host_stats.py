@@ -31,3 +31,54 @@ def test_h1_table_counts():
     assert t[0]["segments"] == 4 and t[0]["detection_probability"] == 0.5
     assert t[0]["truth_above_eta"] == 3 and t[0]["l_dp"] == pytest.approx(1 / 3)
     assert t[1]["detection_probability"] == 1.0 and t[1]["l_dp"] == 0.0
+
+
+def test_h1_table_rejects_duplicate_segments():
+    """Two outputs holding the same segment of one SNR (e.g. a rerun) are an
+    error, not a silent overwrite that would shrink the sample."""
+    from paper_2002_02150_amd.detection import h1_table
+    a = {"snr": 10.0, "values": {0: {"rho": 9.5, "rho0": 9.6}, 1: {"rho": 9.0, "rho0": 9.4}}}
+    b = {"snr": 10.0, "values": {1: {"rho": 9.8, "rho0": 9.7}}}
+    with pytest.raises(ValueError):
+        h1_table(9.2, [a, b])
+
+
+def test_chirp_duration_of_the_papers_binary():
+    """The search modules place the paper's signals by the time from f_* to
+    coalescence: 1.5 + 1.5 Msun from f_* = 10 Hz lasts 15.1 min (Sec. V), and
+    it agrees with the oracle's chirp-time sum."""
+    import json
+    import os
+    from oracle import fitness as F
+    from paper_2002_02150_amd.params import chirp_duration
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_chirp_example.json")))
+    d = chirp_duration(g["m1_msun"], g["m2_msun"], g["f_star_hz"])
+    assert round(d / 60.0, g["duration_printed_digits"]) == g["duration_min"]
+    t0, t15 = F.chirp_times_from_masses(1.4, 1.7, 30.0)
+    t1, t2 = F.higher_chirp_times(t0, t15, 30.0)
+    assert chirp_duration(1.4, 1.7, 30.0) == pytest.approx(t0 + t1 - t15 + t2, rel=1e-12)
+
+
+def test_paper_sources_are_the_printed_locations():
+    """L4 and L5 of Sec. V: alpha, delta in degrees, psi = 30 deg, 1.5 + 1.5 Msun."""
+    import math
+    import synth
+    rng = np.random.default_rng(0)
+    for name, (a, d) in (("L4", (32.09, -53.86)), ("L5", (150.11, -60.16))):
+        inj = synth.paper_source(name, rng, 123)
+        assert inj["alpha"] == pytest.approx(math.radians(a)) and inj["delta"] == pytest.approx(math.radians(d))
+        assert inj["psi"] == pytest.approx(math.radians(30.0)) and (inj["m1"], inj["m2"]) == (1.5, 1.5)
+        assert inj["tc_sample"] == 123 and -1 <= inj["cos_iota"] <= 1 and 0 <= inj["phi_c"] < 2 * math.pi
+
+
+def test_detection_rows_by_location():
+    """Per-location detection probabilities and losses (the paper's detection
+    table separates L4 and L5)."""
+    from paper_2002_02150_amd.detection import h1_rows
+    r1 = [9.6, 9.0, 9.7, 8.0]
+    r0 = [9.7, 9.6, 9.4, 9.55]
+    row = h1_rows(10.0, r1, r0, ["L4", "L4", "L5", "L5"], 9.5)
+    assert row["segments"] == 4 and row["detection_probability"] == 0.5
+    assert row["l_dp"] == pytest.approx(2 / 3)
+    assert row["by_location"]["L4"]["detection_probability"] == 0.5 and row["by_location"]["L4"]["l_dp"] == 0.5
+    assert row["by_location"]["L5"]["detection_probability"] == 0.5 and row["by_location"]["L5"]["l_dp"] == 1.0

@@ -22,7 +22,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 # ---------------------------------------------------------------- chirp times
 
 def test_paper_duration_of_1p5_1p5_binary():
-    """Sec. IV: 1.5+1.5 Msun from f* = 10 Hz lasts 15.1 min.  The time to
+    """Sec. V: 1.5+1.5 Msun from f* = 10 Hz lasts 15.1 min.  The time to
     coalescence from f* in the chirp-time family is tau0 + tau1 - tau1.5 + tau2,
     so this pins the tau0/tau1.5 definitions and the 1PN / 2PN constants of
     tau1 and tau2 (a wrong constant moves the duration by seconds)."""
