@@ -172,6 +172,25 @@ int fcas_set_segment_range(fcas_ctx* ctx, int32_t seg_id, int64_t j_lo, int64_t 
 int fitness_eval_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg,
                        double* d_fitness, int32_t* d_argmax, void* hip_stream);
 
+/* For callers that cannot allocate device memory at call time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same computation, arguments, results and errors as fitness_eval_batch (the
+ * same kernels; results bitwise equal), with the call's scratch memory (point
+ * descriptors, work lists, pass-2 partials, FFT workspace) taken from a static
+ * array of 64 MiB that the library holds on each GPU it runs on until the
+ * process ends, instead of the context's buffers.  The call allocates nothing.
+ * Limit: the tables take about 0.75 KB + 8 S bytes per point (S = pass-2
+ * partials per point: at most 512 for contexts whose max_samples is at most
+ * 262144) and the rest is FFT workspace, which must hold at least one point of
+ * the longest registered segment (2 N 8 bytes mixed, 2 N 16 bytes FP64: an
+ * hour-long segment does not fit); more points than it holds run in chunks.  A call
+ * beyond the limit fails with FCAS_ECAPACITY before anything is enqueued.
+ * Every call on one GPU, from any context, uses that GPU's one array: calls
+ * whose executions overlap on a GPU race (serialise them on one stream).
+ * Always the two-pass schedule; no per-kernel timing is recorded. */
+int fitness_eval_batch_static(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg,
+                              double* d_fitness, int32_t* d_argmax, void* hip_stream);
+
 /* As fitness_eval_batch, plus d_grad float64 [n][4] = dGamma^2/dtheta with the
  * maximising sample j* held fixed (zero outside the rectangle).  Supports
  * networks whose antenna matrix has rank two, or a single detector. */

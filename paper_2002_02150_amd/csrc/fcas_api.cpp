@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -41,6 +42,33 @@ struct TimedPair {
   hipEvent_t a, b;
 };
 
+// Device memory of fitness_eval_batch_static: point descriptors, work lists,
+// pass-2 partials and FFT workspace of one call, in a fixed array that every
+// GPU the library runs on holds until the process ends.  Host code never uses
+// the array's name as an address: scratch_for_device() looks up each device's
+// copy once, with that device current, and keeps the pointer.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (which must be current).
+int scratch_for_device(int device, void** out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return fail(FCAS_EINVAL, "device %d beyond the library's table", device);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return FCAS_OK;
+}
+
 }  // namespace
 
 struct fcas_ctx {
@@ -67,6 +95,7 @@ struct fcas_ctx {
   double* d_sigma2 = nullptr;    // [FCAS_MAX_DET] scratch for segment registration
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
+  void* d_scratch = nullptr;     // this device's copy of the static scratch array (not owned)
   GradBuffers grad{};
   double* d_pol_grad = nullptr;    // [max_batch][4] polish: gradient at the current points
   double* d_pol_cand = nullptr;    // [max_batch][4] polish trials
@@ -285,6 +314,13 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
     g_last_error = msg;
     return rc;
   }
+  if ((rc = scratch_for_device(device, &c->d_scratch))) {
+    std::string msg = g_last_error;
+    free_all(c);
+    delete c;
+    g_last_error = msg;
+    return rc;
+  }
   int32_t parts2[kNumPlans];
   for (int i = 0; i < kNumPlans; ++i) parts2[i] = kPlans[i].parts2[c->prec];
   if ((e = hipMemcpy(c->d_net, &h, sizeof(NetDesc), hipMemcpyHostToDevice)) != hipSuccess ||
@@ -447,7 +483,8 @@ hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t 
 
 // The device buffers one evaluation call works in: point descriptors,
 // per-plan work lists and their counts, pass-2 partials and the FFT
-// workspace (a context owns one set: own_bufs).
+// workspace.  A context owns one set (own_bufs); fitness_eval_batch_static
+// carves another out of the library's static scratch array.
 struct EvalBufs {
   EvalDesc* evals;
   int32_t* lists;        // [kNumPlans][list_stride]
@@ -616,6 +653,52 @@ int fitness_eval_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const in
   if (n == 0) return FCAS_OK;
   hipSetDevice(ctx->device);
   return enqueue_eval(ctx, n, d_theta, d_seg, d_fitness, d_argmax, (hipStream_t)hip_stream);
+}
+
+int fitness_eval_batch_static(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg,
+                              double* d_fitness, int32_t* d_argmax, void* hip_stream) {
+  int rc = validate_batch(ctx, n, d_theta, d_seg, d_fitness, d_argmax);
+  if (rc) return rc;
+  if (n == 0) return FCAS_OK;
+  if (!ctx->d_scratch) return fail(FCAS_EHIP, "no static scratch on device %d", ctx->device);
+  // carve the call's buffers out of the scratch array, each 256-byte aligned
+  const size_t part_elt = ctx->prec ? 8 : 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = (off + bytes + 255) & ~(size_t)255;
+    return at;
+  };
+  const size_t o_counts = take(sizeof(int32_t) * kNumPlans);
+  const size_t o_lists = take(sizeof(int32_t) * (size_t)kNumPlans * n);
+  const size_t o_evals = take(sizeof(EvalDesc) * (size_t)n);
+  const size_t o_pg = take(part_elt * (size_t)n * ctx->part_stride);
+  const size_t o_pj = take(sizeof(int32_t) * (size_t)n * ctx->part_stride);
+  size_t slot_max = 0;
+  for (int plan = 0; plan < kNumPlans; ++plan)
+    if (ctx->plan_refs[plan] > 0) slot_max = std::max(slot_max, 2 * (size_t)kPlans[plan].n * ctx->elt);
+  if (off + std::max<size_t>(slot_max, 1) > kStaticScratchBytes)
+    return fail(FCAS_ECAPACITY,
+                "static scratch of %zu bytes: the tables of %d points take %zu and the longest registered segment "
+                "needs %zu bytes of workspace",
+                kStaticScratchBytes, n, off, slot_max);
+  unsigned char* base = (unsigned char*)ctx->d_scratch;
+  EvalBufs b{};
+  b.counts = (int32_t*)(base + o_counts);
+  b.lists = (int32_t*)(base + o_lists);
+  b.evals = (EvalDesc*)(base + o_evals);
+  b.part_g = base + o_pg;
+  b.part_j = (int32_t*)(base + o_pj);
+  b.ws = base + off;
+  b.ws_bytes = kStaticScratchBytes - off;
+  b.list_stride = n;
+  hipSetDevice(ctx->device);
+  hipStream_t s = (hipStream_t)hip_stream;
+  // the array keeps whatever the last call on this device left: the list
+  // counts must start at zero
+  hipError_t e = launch_zero_i32(b.counts, kNumPlans, s);
+  if (e != hipSuccess) return hip_fail(e, "zero work-list counts");
+  return enqueue_eval(ctx, b, n, d_theta, d_seg, d_fitness, d_argmax, s, false, false);
 }
 
 int fitness_grad_batch(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t* d_seg, double* d_fitness,

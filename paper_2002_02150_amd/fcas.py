@@ -27,7 +27,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP",
 
 EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_plan_count",
             "fcas_plan_info", "fcas_select_plan", "fcas_set_segment", "fcas_set_segment_range",
-            "fitness_eval_batch", "fitness_grad_batch", "fitness_polish", "pso_init",
+            "fitness_eval_batch", "fitness_eval_batch_static", "fitness_grad_batch", "fitness_polish", "pso_init",
             "pso_step", "pso_best", "pso_best_segments",
             "fcas_inject", "fcas_evaluated", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
 
@@ -86,6 +86,7 @@ def library():
         "fcas_set_segment": ([vp, i32, i64, vp, vp, vp], ctypes.c_int),
         "fcas_set_segment_range": ([vp, i32, i64, i64], ctypes.c_int),
         "fitness_eval_batch": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
+        "fitness_eval_batch_static": ([vp, i32, vp, vp, vp, vp, vp], ctypes.c_int),
         "fitness_grad_batch": ([vp, i32, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "fitness_polish": ([vp, i32, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp], ctypes.c_int),
         "pso_init": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp], ctypes.c_int),
@@ -248,6 +249,17 @@ class Context:
         _want(argmax, torch.int32, (n,), self.device, "argmax")
         _check(library().fitness_eval_batch(self._h, n, _ptr(theta), _ptr(seg), _ptr(fitness), _ptr(argmax),
                                             _stream(self.device)))
+        return fitness, argmax
+
+    def eval_static(self, theta, seg, fitness, argmax):
+        """fitness_eval_batch_static: as eval, into caller-provided outputs, with
+        the call's scratch memory in the library's static per-GPU array (the
+        call allocates nothing; calls on one GPU must not overlap)."""
+        n = self._batch_args(theta, seg)
+        _want(fitness, torch.float64, (n,), self.device, "fitness")
+        _want(argmax, torch.int32, (n,), self.device, "argmax")
+        _check(library().fitness_eval_batch_static(self._h, n, _ptr(theta), _ptr(seg), _ptr(fitness), _ptr(argmax),
+                                                   _stream(self.device)))
         return fitness, argmax
 
     def grad(self, theta, seg, fitness=None, argmax=None, grad=None):
