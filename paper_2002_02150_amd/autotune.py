@@ -5,8 +5,9 @@ fastest choice per length to tuning.json (applied by Context by default).
     python -m paper_2002_02150_amd.autotune [--lengths 131072,262144] [--out PATH]
 
 Timing: fitness batches of `batch` points spread over the search rectangle
-(every point evaluated), HIP events around `reps` back-to-back calls, best of
-three such runs.  The data are random: the cost of an evaluation does not depend
+(every point evaluated; 256 by default, between the 192 points a 320-particle
+swarm keeps inside the rectangle early in a search and the 311 it keeps at the
+end), HIP events around `reps` back-to-back calls, best of three such runs.  The data are random: the cost of an evaluation does not depend
 on the data values.
 """
 from __future__ import annotations
@@ -65,7 +66,7 @@ def time_plan(ctx, plan, g1, g2, xf, psd, theta, seg, reps):
     return min(samples)
 
 
-def autotune(lengths=DEFAULT_LENGTHS, n_det=4, fs=2048.0, batch=320, reps=10, grids=GRIDS, out=fcas.TUNING_PATH,
+def autotune(lengths=DEFAULT_LENGTHS, n_det=4, fs=2048.0, batch=256, reps=10, grids=GRIDS, out=fcas.TUNING_PATH,
              device=0, log=print):
     dev = torch.device("cuda", device)
     pos, ten = _network(n_det, dev)

@@ -93,6 +93,7 @@ struct fcas_ctx {
   int32_t* d_err = nullptr;
   unsigned long long* d_evaluated = nullptr;   // running total of points evaluated
   double* d_sigma2 = nullptr;    // [FCAS_MAX_DET] scratch for segment registration
+  double* d_inject = nullptr;    // [kInjectScratch] partial sums of fcas_inject
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   void* d_scratch = nullptr;     // this device's copy of the static scratch array (not owned)
@@ -179,7 +180,7 @@ int free_all(fcas_ctx* c) {
   for (void* p : c->seg_y) if (p) hipFree(p);
   for (double* p : c->seg_b) if (p) hipFree(p);
   void* bufs[] = {c->d_net, c->d_segs, c->d_evals, c->d_lists, c->d_counts, c->d_part_g,
-                  c->d_part_j, c->d_plan_parts2, c->d_err, c->d_sigma2, c->d_ws,
+                  c->d_part_j, c->d_plan_parts2, c->d_err, c->d_sigma2, c->d_inject, c->d_ws,
                   c->d_pol_grad, c->d_pol_cand, c->d_pol_seg, c->d_pol_f, c->d_pol_j, c->d_evaluated,
                   c->d_done};
   for (void* p : bufs) if (p) hipFree(p);
@@ -301,6 +302,7 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
       (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * c->part_stride)) ||
       (rc = dev_alloc(&c->d_plan_parts2, sizeof(int32_t) * kNumPlans)) ||
       (rc = dev_alloc(&c->d_err, sizeof(int32_t))) || (rc = dev_alloc(&c->d_sigma2, sizeof(double) * FCAS_MAX_DET)) ||
+      (rc = dev_alloc(&c->d_inject, sizeof(double) * kInjectScratch)) ||
       (rc = dev_alloc(&c->d_ws, ws)) || (rc = alloc_grad_buffers(c->grad, B, net->n_det)) ||
       (rc = dev_alloc(&c->d_pol_grad, sizeof(double) * 4 * B)) ||
       (rc = dev_alloc(&c->d_pol_cand, sizeof(double) * 4 * B)) ||
@@ -763,7 +765,7 @@ int fcas_inject(fcas_ctx* ctx, int64_t n_samples, const double* params, double s
   if (k_lo > k_hi) return fail(FCAS_EINVAL, "empty band for %lld samples", (long long)n_samples);
   hipSetDevice(ctx->device);
   hipError_t e = launch_inject(ctx->h_net, params, snr, n_samples, k_lo, k_hi, ctx->cfg.fs_hz / (double)n_samples,
-                               d_psd, ctx->d_sigma2, d_xf, (hipStream_t)hip_stream);
+                               d_psd, ctx->d_inject, ctx->d_sigma2, d_xf, (hipStream_t)hip_stream);
   return e == hipSuccess ? FCAS_OK : hip_fail(e, "injection launch");
 }
 

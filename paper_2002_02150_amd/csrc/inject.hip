@@ -45,26 +45,48 @@ __device__ void injection_setup(const InjectArgs& a, EvalDesc& ev) {
   setup_one(a.net, sg, a.theta, ev);
 }
 
-// network SNR^2 of the unit-amplitude signal: sum_i 4 df sum_B |h|^2 / S (fixed-order reduction)
-__global__ void __launch_bounds__(256) k_inject_norm(InjectArgs a, const double* __restrict__ psd,
-                                                     double* __restrict__ snr2) {
-  __shared__ double red[256];
-  EvalDesc ev;
-  injection_setup(a, ev);
-  double acc = 0.0;
-  for (int i = 0; i < a.net.n_det; ++i)
-    for (int k = a.k_lo + threadIdx.x; k <= a.k_hi; k += 256) {
-      double re, im;
-      injection_bin(a, ev, k, i, &re, &im);
-      acc += (re * re + im * im) / psd[(int64_t)i * a.half + k];
-    }
-  red[threadIdx.x] = acc;
+// Fixed-order tree sum of one value per thread of a 256-thread block.
+__device__ double block_sum256(double x, double* red) {
+  red[threadIdx.x] = x;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) snr2[0] = 4.0 * a.df * red[0];
+  return red[0];
+}
+
+// Network SNR^2 of the unit-amplitude signal, sum_i 4 df sum_B |h|^2 / S, in
+// two fixed-order stages (deterministic): thread t of block b sums the bins
+// k_lo + 256 b + t + m 256 kInjectParts (m = 0, 1, ...) of every detector,
+// the block's tree sum goes to parts[b], then one block adds the parts.
+constexpr int kInjectParts = 256;
+static_assert(kInjectParts == kInjectScratch, "the context's scratch holds one partial per block");
+
+__global__ void __launch_bounds__(256) k_inject_norm_parts(InjectArgs a, const double* __restrict__ psd,
+                                                           double* __restrict__ parts) {
+  __shared__ double red[256];
+  __shared__ EvalDesc ev;
+  if (threadIdx.x == 0) injection_setup(a, ev);
+  __syncthreads();
+  double acc = 0.0;
+  const int stride = kInjectParts * 256;
+  for (int i = 0; i < a.net.n_det; ++i)
+    for (int k = a.k_lo + blockIdx.x * 256 + threadIdx.x; k <= a.k_hi; k += stride) {
+      double re, im;
+      injection_bin(a, ev, k, i, &re, &im);
+      acc += (re * re + im * im) / psd[(int64_t)i * a.half + k];
+    }
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) parts[blockIdx.x] = t;
+}
+
+__global__ void __launch_bounds__(256) k_inject_norm(InjectArgs a, const double* __restrict__ parts,
+                                                     double* __restrict__ snr2) {
+  __shared__ double red[256];
+  static_assert(kInjectParts == 256, "one part per thread");
+  const double t = block_sum256(parts[threadIdx.x], red);
+  if (threadIdx.x == 0) snr2[0] = 4.0 * a.df * t;
 }
 
 __global__ void k_inject_add(InjectArgs a, const double* __restrict__ snr2, double* __restrict__ xf) {
@@ -83,7 +105,8 @@ __global__ void k_inject_add(InjectArgs a, const double* __restrict__ snr2, doub
 }
 
 hipError_t launch_inject(const NetDesc& net, const double* params, double snr, int64_t n_samples, int k_lo,
-                         int k_hi, double df, const double* psd, double* snr2_scratch, double* xf, hipStream_t s) {
+                         int k_hi, double df, const double* psd, double* parts_scratch, double* snr2_scratch,
+                         double* xf, hipStream_t s) {
   InjectArgs a{};
   a.net = net;
   for (int d = 0; d < 4; ++d) a.theta[d] = params[d];
@@ -96,7 +119,8 @@ hipError_t launch_inject(const NetDesc& net, const double* params, double snr, i
   a.k_lo = k_lo;
   a.k_hi = k_hi;
   a.df = df;
-  hipLaunchKernelGGL(k_inject_norm, dim3(1), dim3(256), 0, s, a, psd, snr2_scratch);
+  hipLaunchKernelGGL(k_inject_norm_parts, dim3(kInjectParts), dim3(256), 0, s, a, psd, parts_scratch);
+  hipLaunchKernelGGL(k_inject_norm, dim3(1), dim3(256), 0, s, a, parts_scratch, snr2_scratch);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int K = k_hi - k_lo + 1;

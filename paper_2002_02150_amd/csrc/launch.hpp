@@ -71,8 +71,11 @@ hipError_t launch_segment_prep(int precision, const double* xf, const double* ps
                                int n_det, int64_t half, int k_lo, int k_hi, double df, double f_star,
                                void* y_out, double* b_out, hipStream_t s);
 
-// synthetic signal: params = (alpha, delta, tau0, tau1.5, psi, phi_c, cos_iota, t_c [s])
+// synthetic signal: params = (alpha, delta, tau0, tau1.5, psi, phi_c, cos_iota, t_c [s]);
+// parts_scratch holds kInjectParts (256) partial sums
+constexpr int kInjectScratch = 256;
 hipError_t launch_inject(const NetDesc& net, const double* params, double snr, int64_t n_samples, int k_lo,
-                         int k_hi, double df, const double* psd, double* snr2_scratch, double* xf, hipStream_t s);
+                         int k_hi, double df, const double* psd, double* parts_scratch, double* snr2_scratch,
+                         double* xf, hipStream_t s);
 
 }  // namespace fcas

@@ -56,7 +56,15 @@ using Rad = Radices<R...>;
   X(26, 3686400,   64, 8, (8, 8),       32, 32,  256, 8, (8, 8, 4),       8, 8, 225, 15, (15, 15), 16, 8) \
   X(27, 7372800,   64, 8, (8, 8),       32, 32,  512, 8, (8, 8, 8),       4, 4, 225, 15, (15, 15), 16, 8) \
   X(28, 7372800,  128, 8, (8, 4, 4),    16, 16,  256, 8, (8, 8, 4),       8, 8, 225, 15, (15, 15), 16, 8) \
-  X(29, 3686400,  256, 8, (8, 8, 4),    8, 8,     64, 8, (8, 8),          32, 32, 225, 15, (15, 15), 16, 8)
+  X(29, 3686400,  256, 8, (8, 8, 4),    8, 8,     64, 8, (8, 8),          32, 32, 225, 15, (15, 15), 16, 8) \
+  /* 512-thread pass 1 (twice the columns: 128- or 256-byte store segments)   */                 \
+  X(30, 131072,   256, 8, (8, 8, 4),    16, 16,  512, 8, (8, 8, 8),       4, 4, 1, 1, (1), 1, 1) \
+  X(31, 262144,   256, 8, (8, 8, 4),    16, 16, 1024, 8, (8, 8, 8, 2),    2, 2, 1, 1, (1), 1, 1) \
+  X(32,  65536,   128, 8, (8, 4, 4),    32, 32,  512, 8, (8, 8, 8),       4, 4, 1, 1, (1), 1, 1) \
+  X(33, 196608,   256, 8, (8, 8, 4),    16, 16,  768, 12, (4, 4, 4, 4, 3), 4, 4, 1, 1, (1), 1, 1) \
+  X(34, 131072,   128, 8, (8, 4, 4),    16, 16, 1024, 16, (16, 16, 4),    4, 2, 1, 1, (1), 1, 1) \
+  X(35, 262144,   512, 8, (8, 8, 8),    8, 8,    512, 8, (8, 8, 8),       4, 4, 1, 1, (1), 1, 1) \
+  X(36, 262144,   512, 8, (8, 8, 8),    16, 8,   512, 8, (8, 8, 8),       4, 4, 1, 1, (1), 1, 1)
 // clang-format on
 
 #define FCAS_UNPAREN(...) __VA_ARGS__
@@ -71,7 +79,7 @@ using Rad = Radices<R...>;
 
 FCAS_PLAN_LIST(FCAS_DECLARE_PLAN)
 
-constexpr int kNumPlans = 30;
+constexpr int kNumPlans = 37;
 
 struct PlanInfo {
   int64_t n;

@@ -122,6 +122,14 @@ def h1_rows(snr, r1, r0, loc, eta):
     locs = sorted(set(loc.tolist()))
     if len(locs) > 1:
         row["by_location"] = {l: stats(loc == l) for l in locs}
+    if len(locs) == 2:
+        # Sec. V: two-sample Kolmogorov-Smirnov test of the two locations' rho'
+        # samples, on all of them and on those above 9.0 only
+        from scipy.stats import ks_2samp
+        a, b = r1[loc == locs[0]], r1[loc == locs[1]]
+        row["ks_pvalue_locations"] = float(ks_2samp(a, b).pvalue)
+        a9, b9 = a[a > 9.0], b[b > 9.0]
+        row["ks_pvalue_locations_above_9"] = float(ks_2samp(a9, b9).pvalue) if len(a9) and len(b9) else None
     return row
 
 

@@ -21,7 +21,8 @@ BIN = os.path.join(ROOT, "tests", "emu", "_build", "fcas_emu")
 PLANS = {0: 2048, 1: 4096, 2: 8192, 3: 16384, 4: 32768, 5: 65536, 6: 131072, 7: 262144,
          8: 24576, 9: 49152, 10: 98304, 11: 196608,
          12: 131072, 13: 131072, 14: 131072, 15: 131072, 16: 262144, 17: 65536, 18: 196608, 19: 8192,
-         20: 262144, 21: 196608, 22: 65536, 23: 65536, 24: 131072, 25: 460800, 26: 3686400, 27: 7372800, 28: 7372800, 29: 3686400}
+         20: 262144, 21: 196608, 22: 65536, 23: 65536, 24: 131072, 25: 460800, 26: 3686400, 27: 7372800, 28: 7372800, 29: 3686400,
+         30: 131072, 31: 262144, 32: 65536, 33: 196608, 34: 131072, 35: 262144, 36: 262144}
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +61,8 @@ def _run(emu, tmp_path, case, theta, plan, prec):
     (18, "HLVK", 0), (19, "HL", 0), (12, "HLVK", 1), (18, "HL", 1), (20, "HLVK", 0), (20, "HL", 1),
     (21, "HLVK", 0), (22, "HLV", 0), (23, "HLVK", 0), (24, "HLVK", 0), (21, "HL", 1), (24, "HL", 1),
     (25, "HLVK", 0), (25, "HL", 1), (27, "HLVK", 0), (29, "HL", 1),
+    (30, "HLVK", 0), (30, "HL", 1), (31, "HLVK", 0), (32, "HLVK", 0), (33, "HLVK", 0), (34, "HLVK", 0),
+    (35, "HLVK", 0), (36, "HLVK", 0), (36, "HL", 1),
     # five and six detectors (a site repeated: a co-located pair with its own
     # noise) take the kernels' run-time detector loop
     (6, "HLVKH", 0), (25, "HLVKHL", 0), (2, "HLVKHL", 1),

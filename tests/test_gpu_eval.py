@@ -131,15 +131,18 @@ def test_ragged_segments_in_one_call():
     ctx.close()
 
 
-@pytest.mark.parametrize("plan", [7, 16, 20])
-def test_eval_plans_262144_sampled(plan):
-    """Every plan of the 128-s segments (512 x 512, 256 x 1024 with 16-element
-    rows, and 256 x 1024 with rows of 8-element threads spanning two
-    wavefronts) matches the oracle on sampled points of a full-size batch."""
+@pytest.mark.parametrize("plan", [7, 16, 20, 31, 35, 36, 6, 12, 13, 14, 15, 24, 30, 34, 11, 18, 21, 33, 5, 17, 22,
+                                  23, 32])
+def test_eval_plans_sampled(plan):
+    """Every plan of the 32-s to 128-s segments (65536 to 262144 samples:
+    column lengths 128 to 512, 8- and 16-element threads, 256- to 1024-thread
+    work-groups, rows in one or two wavefronts) matches the oracle on sampled
+    points of a 16-point batch."""
     require_gpu()
     from paper_2002_02150_amd.fcas import plans
-    assert dict(plans())[plan]["n"] == 262144
-    case = Case("HLVK", 262144, 2048.0, snr=10.0, cfg=2, realization=plan)
+    n = dict(plans())[plan]["n"]
+    assert n in (65536, 131072, 196608, 262144)
+    case = Case("HLVK", n, 2048.0, snr=10.0, cfg=2, realization=plan)
     rng = np.random.default_rng(plan)
     th = thetas_for(case, rng, n_near=8, n_uniform=8, extras=False)
     ctx = make_ctx(case, 0, max_batch=len(th))

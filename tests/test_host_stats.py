@@ -82,3 +82,31 @@ def test_detection_rows_by_location():
     assert row["l_dp"] == pytest.approx(2 / 3)
     assert row["by_location"]["L4"]["detection_probability"] == 0.5 and row["by_location"]["L4"]["l_dp"] == 0.5
     assert row["by_location"]["L5"]["detection_probability"] == 0.5 and row["by_location"]["L5"]["l_dp"] == 1.0
+
+
+def _ks_perm_pvalue(a, b):
+    """Exact two-sample KS p-value by enumeration: the fraction of the splits
+    of the pooled sample into groups of len(a) and len(b) whose statistic is at
+    least the observed one (distinct values, so the split fixes the ranks)."""
+    import itertools
+    pool = sorted(a + b)
+
+    def d(x, y):
+        return max(abs(sum(v <= t for v in x) / len(x) - sum(v <= t for v in y) / len(y)) for t in pool)
+    d0 = d(a, b)
+    splits = list(itertools.combinations(range(len(pool)), len(a)))
+    hits = sum(d([pool[i] for i in c], [pool[i] for i in range(len(pool)) if i not in c]) >= d0 - 1e-12
+               for c in splits)
+    return hits / len(splits)
+
+
+def test_detection_rows_location_ks_test():
+    """The two-sample KS test between the locations' rho' samples (Sec. V),
+    on all values and on those above 9.0, against the exact permutation
+    p-value by enumeration."""
+    from paper_2002_02150_amd.detection import h1_rows
+    a, b = [8.0, 9.1, 9.2, 9.3], [8.5, 9.4, 9.5, 9.6]
+    row = h1_rows(9.0, a + b, [10.0] * 8, ["L4"] * 4 + ["L5"] * 4, 9.5)
+    assert row["ks_pvalue_locations"] == pytest.approx(_ks_perm_pvalue(a, b), rel=1e-9)
+    assert row["ks_pvalue_locations_above_9"] == pytest.approx(_ks_perm_pvalue(a[1:], b[1:]), rel=1e-9)
+    assert row["ks_pvalue_locations_above_9"] == pytest.approx(0.1)      # 2 of the 20 splits of 3 + 3 separate fully
