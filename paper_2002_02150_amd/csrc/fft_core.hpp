@@ -143,6 +143,48 @@ FCAS_HD void stream_store(cplx<R>* p, cplx<R> v) {
 #endif
 }
 
+// Non-temporal stores into one region of the workspace through a buffer
+// resource (base and size in scalar registers).  A store's byte offset is a
+// per-thread part (a vector register) plus a uniform part (a scalar register
+// or constant), so the stores of a thread at compile-time strides share one
+// address computation instead of a 64-bit address each.  The region is at
+// most 2^32 - 1 bytes; the hardware drops a store past its end.
+template <typename R>
+struct StreamOut {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __amdgpu_buffer_rsrc_t rs;
+  FCAS_HD StreamOut(cplx<R>* base, int64_t elems)
+      : rs(__builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(elems * (int64_t)sizeof(cplx<R>)), kRsrcWord3)) {}
+  // element `vo + so` of the region, vo per thread, so uniform
+  FCAS_HD void store(int vo, int so, cplx<R> v) const {
+    if constexpr (sizeof(R) == 4) {
+      typedef int i2 __attribute__((ext_vector_type(2)));
+      i2 t;
+      t.x = __builtin_bit_cast(int, v.x);
+      t.y = __builtin_bit_cast(int, v.y);
+      __builtin_amdgcn_raw_buffer_store_b64(t, rs, vo * (int)sizeof(cplx<R>), so * (int)sizeof(cplx<R>), kNt);
+    } else {
+      typedef int i4 __attribute__((ext_vector_type(4)));
+      const long long xr = __builtin_bit_cast(long long, v.x), yr = __builtin_bit_cast(long long, v.y);
+      i4 t;
+      t.x = (int)xr;
+      t.y = (int)(xr >> 32);
+      t.z = (int)yr;
+      t.w = (int)(yr >> 32);
+      __builtin_amdgcn_raw_buffer_store_b128(t, rs, vo * (int)sizeof(cplx<R>), so * (int)sizeof(cplx<R>), kNt);
+    }
+  }
+  // descriptor word 3 of an untyped gfx9 buffer (32-bit data format); cache
+  // policy of the stores: non-temporal
+  static constexpr int kRsrcWord3 = 0x00020000;
+  static constexpr int kNt = 2;
+#else
+  cplx<R>* base;
+  FCAS_HD StreamOut(cplx<R>* b, int64_t) : base(b) {}
+  FCAS_HD void store(int vo, int so, cplx<R> v) const { base[(int64_t)vo + so] = v; }
+#endif
+};
+
 // ---------------------------------------------------------------------------
 // Small inverse DFTs in registers: x[0..R) -> X[0..R), X[j] = sum_p x[p] w_R^{pj}
 // ---------------------------------------------------------------------------

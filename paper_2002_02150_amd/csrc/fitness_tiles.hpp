@@ -50,7 +50,8 @@ struct EvalDesc {
   double q[kMaxDet][2];       // orthonormal basis of span(diag(sigma) U), FP64
   float qf[kMaxDet][2];       // same, rounded to float
   double v[kMaxDet][2];       // V = diag(sigma) U (kept for the gradient)
-  double step1[kMaxDet][2];   // exp(2 pi i dk1 dly_i): delay ramp across one pass-1 register stride
+  double step1[kMaxDet][2];   // exp(2 pi i dk1 (dly_i - dly_0)): ramp of detector i relative to
+                              // detector 0 across one pass-1 register stride
   float step1f[kMaxDet][2];   // same, rounded to float
   int32_t seg;
   int32_t status;             // 1 evaluate, 0 outside the rectangle, -2 bad segment
@@ -107,11 +108,17 @@ FCAS_HD void setup_point(const NetDesc& net, const double* th, double coef[4], S
   fr.ey[0] = -sd * ca; fr.ey[1] = -sd * sa; fr.ey[2] = cd;
 }
 
-// Detector i: delay ramp (cycles per bin), its pass-1 step, and row i of V.
-FCAS_HD void setup_detector(const NetDesc& net, const SegDesc& sg, const SkyFrame& fr, int i, EvalDesc& ev) {
+// Delay ramp of detector i in cycles per bin (delay relative to the geocentre).
+FCAS_HD double detector_delay(const NetDesc& net, const SegDesc& sg, const SkyFrame& fr, int i) {
   const double* r = net.pos[i];
-  ev.dly[i] = -(fr.n[0] * r[0] + fr.n[1] * r[1] + fr.n[2] * r[2]) / kC * sg.df;
-  const double ps = (double)sg.dk1 * ev.dly[i];
+  return -(fr.n[0] * r[0] + fr.n[1] * r[1] + fr.n[2] * r[2]) / kC * sg.df;
+}
+
+// Detector i: delay ramp (cycles per bin), its pass-1 step relative to
+// detector 0, and row i of V.
+FCAS_HD void setup_detector(const NetDesc& net, const SegDesc& sg, const SkyFrame& fr, int i, EvalDesc& ev) {
+  ev.dly[i] = detector_delay(net, sg, fr, i);
+  const double ps = (double)sg.dk1 * (ev.dly[i] - detector_delay(net, sg, fr, 0));
   double ss, cs;
   sincos_rev(ps - rint(ps), &ss, &cs);
   ev.step1[i][0] = cs;
@@ -344,13 +351,17 @@ FCAS_HD int row_base(int row) {
 // (k1 >= N1/2) are always zero and are left unset: the first stage reads
 // only the lower half.
 //
-// With e_c(k) = exp(2 pi i Phi_k) (FP64 phase, one sine/cosine per bin) and
-// the delay ramps r_i(k) = exp(2 pi i k dly_i),
-//   W_m(k) = e_c(k) sum_i Q_im y^i_k r_i(k).
-// r_i is exact (FP64-reduced) at the thread's first bin and advanced by the
-// constant factor exp(2 pi i (P1 W1) dly_i) of the point's descriptor from
-// register to register.  Out-of-band registers read bin k_lo (any finite
-// value) and are cleared by a zero e_c, so no lane branches.
+// With the delay ramps r_i(k) = exp(2 pi i k dly_i) and the template phase
+// Phi_k, W_m(k) = exp(2 pi i Phi_k) sum_i Q_im y^i_k r_i(k).  Detector 0's ramp
+// is taken out of the sum into the common factor,
+//   W_m(k) = e(k) [Q_0m y^0_k + sum_{i>0} Q_im y^i_k r'_i(k)],
+//   e(k) = exp(2 pi i (Phi_k + k dly_0)),  r'_i(k) = exp(2 pi i k (dly_i - dly_0)),
+// so detector 0 needs no ramp.  e is one sine/cosine per bin of an FP64 phase
+// reduced mod 1; r'_i is exact (FP64-reduced) at the thread's first bin and
+// advanced by the constant factor exp(2 pi i (P1 W1)(dly_i - dly_0)) of the
+// point's descriptor from register to register.  Out-of-band registers read
+// bin k_lo (any finite value) and are cleared by a zero e, so no lane
+// branches.
 // ---------------------------------------------------------------------------
 // Segment data one pass-1 thread needs for a work item: y of its in-band
 // registers and detectors, and the basis b of those bins (DT > 0 only).
@@ -418,20 +429,21 @@ FCAS_HD Pass1Point<Real, DT> pass1_point(P ev) {
   return r;
 }
 
-// exp(2 pi i Phi) for an in-band bin with basis value b, 0 otherwise (Ev: a
-// descriptor with the phase coefficients `coef`).
+// e(k) = exp(2 pi i (Phi_k + k dly_0)) for an in-band bin k with basis value
+// b, 0 otherwise (Ev: a descriptor with the phase coefficients `coef` and the
+// delay ramps `dly`).
 template <typename Real, class Ev>
-FCAS_HD cplx<Real> band_phase(const Ev& ev, double b, bool in) {
-  const double ph = common_phase(ev.coef, b);
+FCAS_HD cplx<Real> band_phase(const Ev& ev, double b, int k, bool in) {
+  const double ph = common_phase(ev.coef, b) + (double)k * ev.dly[0];
   Real s, cc;
   sincos_rev((Real)(ph - rint(ph)), &s, &cc);
   return in ? mk<Real>(cc, s) : mk<Real>(0, 0);
 }
 
-// Delay ramp of detector i at the thread's first bin k0 (FP64 reduction).
+// Ramp r'_i of detector i > 0 at the thread's first bin k0 (FP64 reduction).
 template <typename Real, class Ev>
 FCAS_HD cplx<Real> first_ramp(const Ev& ev, int i, int k0) {
-  const double ph0 = (double)k0 * ev.dly[i];
+  const double ph0 = (double)k0 * (ev.dly[i] - ev.dly[0]);
   Real s, cc;
   sincos_rev((Real)(ph0 - rint(ph0)), &s, &cc);
   return mk<Real>(cc, s);
@@ -442,13 +454,17 @@ template <typename Real, class PL, int DT>
 FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL, DT>& d,
                            const Pass1Point<Real, DT>& ev) {
   constexpr int QH = PL::E1 / 2;
+  {
+    const Real q0 = ev.q[0][0], q1 = ev.q[0][1];
 #pragma unroll
-  for (int q = 0; q < QH; ++q) {
-    v[0][q] = mk<Real>(0, 0);
-    v[1][q] = mk<Real>(0, 0);
+    for (int q = 0; q < QH; ++q) {
+      const cplx<Real> u = d.y[0][q];
+      v[0][q] = mk<Real>(q0 * u.x, q0 * u.y);
+      v[1][q] = mk<Real>(q1 * u.x, q1 * u.y);
+    }
   }
 #pragma unroll
-  for (int i = 0; i < DT; ++i) {
+  for (int i = 1; i < DT; ++i) {
     cplx<Real> ramp = first_ramp<Real>(ev, i, d.k0);
     const cplx<Real> step = mk<Real>(ev.step[i][0], ev.step[i][1]);
     const Real q0 = ev.q[i][0], q1 = ev.q[i][1];
@@ -462,7 +478,7 @@ FCAS_HD void pass1_compute(cplx<Real> (&v)[2][PL::E1], const Pass1Data<Real, PL,
   }
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
-    const cplx<Real> e = band_phase<Real>(ev, d.b[q], d.in[q]);
+    const cplx<Real> e = band_phase<Real>(ev, d.b[q], d.k0 + q * PL::DK1, d.in[q]);
     v[0][q] = mul(v[0][q], e);
     v[1][q] = mul(v[1][q], e);
   }
@@ -486,11 +502,18 @@ FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, cons
     const int k = k0 + q * DK;
     in[q] = (k >= sg.k_lo) && (k <= sg.k_hi);
     kk[q] = in[q] ? k - sg.k_lo : 0;
-    v[0][q] = mk<Real>(0, 0);
-    v[1][q] = mk<Real>(0, 0);
+  }
+  {
+    const Real q0 = Basis<Real>::get(ev, 0, 0), q1 = Basis<Real>::get(ev, 0, 1);
+#pragma unroll
+    for (int q = 0; q < QH; ++q) {
+      const cplx<Real> u = y[(int64_t)kk[q] * n_det];
+      v[0][q] = mk<Real>(q0 * u.x, q0 * u.y);
+      v[1][q] = mk<Real>(q1 * u.x, q1 * u.y);
+    }
   }
 #pragma unroll
-  for (int i = 0; i < (DT > 0 ? DT : kMaxDet); ++i) {
+  for (int i = 1; i < (DT > 0 ? DT : kMaxDet); ++i) {
     if (DT == 0 && i >= n_det) break;
     cplx<Real> ramp = first_ramp<Real>(ev, i, k0);
     const cplx<Real> step = ramp_step<Real>(ev, i);
@@ -505,7 +528,7 @@ FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, cons
   }
 #pragma unroll
   for (int q = 0; q < QH; ++q) {
-    const cplx<Real> e = band_phase<Real>(ev, sg.b[kk[q]], in[q]);
+    const cplx<Real> e = band_phase<Real>(ev, sg.b[kk[q]], k0 + q * DK, in[q]);
     v[0][q] = mul(v[0][q], e);
     v[1][q] = mul(v[1][q], e);
   }
@@ -515,13 +538,13 @@ FCAS_HD void pass1_prologue(cplx<Real> (&v)[2][PL::E1], const EvalDesc& ev, cons
 // the next pass loads the rows).
 template <typename Real, class PL>
 FCAS_HD void pass1_store(cplx<Real> (&v)[2][PL::E1], cplx<Real>* slot, int tile, int c, int p) {
-  const int k2 = tile * PL::C + c;
+  static_assert(2 * (int64_t)PL::N * sizeof(cplx<Real>) < (int64_t(1) << 31), "byte offsets fit in 31 bits");
+  const StreamOut<Real> out(slot, 2 * (int64_t)PL::N);
+  const int o = p * PL::W1 + tile * PL::C + c;      // row j1 = p, column k2
 #pragma unroll
   for (int q = 0; q < PL::E1; ++q) {
-    const int j1 = p + q * PL::P1;
-    const int64_t o = (int64_t)j1 * PL::W1 + k2;
-    stream_store(slot + o, v[0][q]);
-    stream_store(slot + PL::N + o, v[1][q]);
+    out.store(o, q * PL::P1 * PL::W1, v[0][q]);       // row j1 = p + q P1
+    out.store(o, PL::N + q * PL::P1 * PL::W1, v[1][q]);
   }
 }
 

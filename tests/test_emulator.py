@@ -31,8 +31,11 @@ def emu():
     if not os.path.exists(BIN) or os.path.getmtime(BIN) < max(os.path.getmtime(d) for d in deps):
         os.makedirs(os.path.dirname(BIN), exist_ok=True)
         # -O0: the optimiser takes minutes over every plan instantiation, the runs take seconds either way
+        # built under a private name and renamed, so that parallel test workers never run a half-written binary
+        tmp = f"{BIN}.{os.getpid()}"
         subprocess.run(["g++", "-std=c++17", "-O0", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
-                        "-I" + CSRC, SRC, "-o", BIN], check=True)
+                        "-I" + CSRC, SRC, "-o", tmp], check=True)
+        os.replace(tmp, BIN)
     return BIN
 
 
