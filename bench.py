@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=1280,
                     help="points the oracle evaluates for cpu_baseline (the first 320 also for parity)")
     ap.add_argument("--schedule", choices=("fused", "two-pass"), default="two-pass")
+    ap.add_argument("--tail", choices=("fused", "separate"), default="fused",
+                    help="end of a PSO iteration in captured steps: one kernel (pso_run) or the separate finalize, "
+                         "swarm-update and set-up kernels (fitness_eval_batch + pso_step)")
     ap.add_argument("--config", choices=("search", "batched", "gradient", "sweep", "hour"), default="search",
                     help="search: the benchmark configuration (default); batched: 256 ragged segments, "
                          "40 particles x 4 runs each; gradient: 4096 fitness gradients near a true source; "
@@ -102,8 +105,8 @@ class Search:
     iteration is the fitness of all particles and the swarm update; after the
     iterations the best of the runs is taken and that point polished."""
 
-    def __init__(self, torch, ctx, sw):
-        self.torch, self.ctx, self.sw = torch, ctx, sw
+    def __init__(self, torch, ctx, sw, fused_tail=True):
+        self.torch, self.ctx, self.sw, self.fused_tail = torch, ctx, sw, fused_tail
         n = RUNS * PARTICLES
         dev = ctx.device
         self.seg = torch.zeros(n, dtype=torch.int32, device=dev)
@@ -121,22 +124,30 @@ class Search:
         self.ctx.set_timing(False)
         self.sw.step(self.f, self.j)
 
+    def iterations(self, k):
+        """k iterations: one pso_run call (the fused end of iteration), or k
+        alternations of the fitness call and the swarm update."""
+        if self.fused_tail:
+            self.sw.run(k, self.seg, self.f, self.j)
+        else:
+            for _ in range(k):
+                self.iteration()
+
     def capture(self, group):
         """Captures two HIP graphs: `group` iterations, and one iteration."""
         torch = self.torch
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.iteration()
+            self.iterations(1)
         torch.cuda.current_stream().wait_stream(s)
         self.group = group
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
-            for _ in range(group):
-                self.iteration()
+            self.iterations(group)
         self.graph1 = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph1):
-            self.iteration()
+            self.iterations(1)
 
     def run(self, steps):
         """`steps` iterations as graph replays."""
@@ -284,8 +295,11 @@ def run_batched(a, torch, dev):
     sw.init()
 
     def iteration():
-        ctx.eval(sw.theta, seg, f, j)
-        sw.step(f, j)
+        if a.tail == "fused":
+            sw.run(1, seg, f, j)
+        else:
+            ctx.eval(sw.theta, seg, f, j)
+            sw.step(f, j)
 
     for _ in range(a.warmup):
         iteration()
@@ -456,7 +470,7 @@ def run_hour(a, torch, dev):
     ctx.set_segment(0, xf, psd_d)
     sw = Swarm(ctx, PsoConfig(n_runs=RUNS, n_particles=PARTICLES, n_iter=1000, seed=20020215))
     first_batch = sw.init().clone()
-    search = Search(torch, ctx, sw)
+    search = Search(torch, ctx, sw, fused_tail=a.tail == "fused")
     for _ in range(a.warmup):
         search.iteration()
     search.capture(GRAPH_GROUP)
@@ -572,7 +586,7 @@ def main():
     ctx, net, xf, psd_d, inj = make_workload(torch, dev, a.schedule)
     sw = Swarm(ctx, PsoConfig(n_runs=RUNS, n_particles=PARTICLES, n_iter=2000, seed=20020215))
     first_batch = sw.init().clone()
-    search = Search(torch, ctx, sw)
+    search = Search(torch, ctx, sw, fused_tail=a.tail == "fused")
     for _ in range(a.warmup):
         search.iteration()
     search.capture(GRAPH_GROUP)   # one more iteration, then graphs of GRAPH_GROUP and 1 iterations
@@ -655,7 +669,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "avg_launch_ms": avg_ms, "alg_bytes_per_launch": alg},
         "kernel_ms_per_step": {"k_pass1": avg1, "k_pass2": avg2, "k_fused": avgf},
-        "schedule": a.schedule,
+        "schedule": a.schedule, "tail": a.tail,
         "eager_value": (ev3 - ev2) / dt2, "points_per_launch": pts,
         "kernel_hash": kernel_hash(),
         "points_per_s": evals / dt, "evaluated_fraction": particle_evals / evals,

@@ -248,6 +248,21 @@ int pso_init(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s,
 int pso_step(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s,
              const double* d_fitness, const int32_t* d_argmax, double* d_theta_next, void* hip_stream);
 
+/* n_iter iterations of the swarm (Sec. III), each the fitness of the current
+ * points followed by the swarm update: the same results, bit for bit, as
+ * n_iter alternations of fitness_eval_batch and pso_step on these arrays.
+ * d_theta float64 [R*P][4] holds the current points on entry (those pso_init
+ * or the previous pso_step / pso_run wrote) and the next points on return;
+ * d_seg int32 [R*P] the segment of every particle; d_fitness float64 [R*P]
+ * and d_argmax int32 [R*P] receive the last iteration's fitness and samples.
+ * An iteration takes the FFT passes and one more launch, which finalizes the
+ * fitness of every run's points, moves the swarm and sets up the next
+ * points (one work-group per run, for n_particles <= 128; larger runs take
+ * the separate kernels).  FCAS_ECAPACITY if R*P > max_batch.  Asynchronous;
+ * capturable (the iteration count lives on the device); no timing events. */
+int pso_run(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, int32_t n_iter, double* d_theta,
+            const int32_t* d_seg, double* d_fitness, int32_t* d_argmax, void* hip_stream);
+
 /* Best of the M independent runs (Sec. III): d_out_f float64 [1] (the
  * coherent search statistic squared), d_out_theta float64 [4], d_out_j int32
  * [1] (coalescence sample), d_out_run int32 [1] (lowest run on ties). */

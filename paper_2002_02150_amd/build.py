@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libfcas.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["fcas_api.cpp", "setup.hip", "eval_f32.hip", "eval_f64.hip", "grad.hip", "pso.hip", "inject.hip"]
+SOURCES = ["fcas_api.cpp", "setup.hip", "eval_f32.hip", "eval_f64.hip", "grad.hip", "pso.hip", "inject.hip", "tail.hip"]
 ARCH = os.environ.get("FCAS_OFFLOAD_ARCH", "gfx950")
 
 

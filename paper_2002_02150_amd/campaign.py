@@ -26,9 +26,9 @@ def search_segments(ctx, n_seg, runs=8, particles=40, iters=2000, seed=20020215,
     f = torch.empty(n, dtype=torch.float64, device=dev)
     j = torch.empty(n, dtype=torch.int32, device=dev)
 
-    def iteration():
-        ctx.eval(sw.theta, seg, f, j)
-        sw.step(f, j)
+    def iterations(k):
+        # k iterations (fitness, then swarm update) in one pso_run call
+        sw.run(k, seg, f, j)
 
     group = min(20, iters)
     torch.cuda.synchronize(dev)
@@ -37,15 +37,14 @@ def search_segments(ctx, n_seg, runs=8, particles=40, iters=2000, seed=20020215,
     st = torch.cuda.Stream(dev)
     st.wait_stream(torch.cuda.current_stream(dev))
     with torch.cuda.stream(st):
-        iteration()                       # iteration 1, eagerly, before the capture
+        iterations(1)                     # iteration 1, eagerly, before the capture
     torch.cuda.current_stream(dev).wait_stream(st)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
-        for _ in range(group):
-            iteration()
+        iterations(group)
     graph1 = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph1):
-        iteration()
+        iterations(1)
     rest = iters - 1
     for g in range(rest // group):
         graph.replay()

@@ -452,28 +452,14 @@ __global__ void __launch_bounds__(PL::T2)
 // ---------------------------------------------------------------------------
 // Finalize: one wavefront per point reduces its pass-2 partials.
 // ---------------------------------------------------------------------------
+// Gamma^2 and j* of point e from its partials, by the 64 lanes of one
+// wavefront (lane 0 writes them); -inf / -1 outside the rectangle, NaN / -2
+// for a bad segment.
 template <typename Real>
-__global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ evals,
-                                                  const SegDesc* __restrict__ segs, const Real* __restrict__ part_g,
-                                                  const int32_t* __restrict__ part_j, int n, int part_stride,
-                                                  const int32_t* __restrict__ plan_parts2,
-                                                  int32_t* __restrict__ counts,
-                                                  unsigned long long* __restrict__ evaluated,
-                                                  double* __restrict__ fitness, int32_t* __restrict__ argmax) {
-  const int lane = threadIdx.x & 63;
-  const int e = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    // running total of points evaluated (inside the rectangle); the passes of
-    // this call are done with the list counts, which start the next call at 0
-    unsigned long long t = 0;
-    for (int p = 0; p < kNumPlans; ++p) {
-      t += (unsigned long long)counts[p];
-      counts[p] = 0;
-    }
-    atomicAdd(evaluated, t);
-  }
-  if (e >= n) return;
-  const EvalDesc& ev = evals[e];
+__device__ __forceinline__ void finalize_point(const EvalDesc& ev, const Real* __restrict__ part_g,
+                                               const int32_t* __restrict__ part_j, int part_stride,
+                                               const int32_t* __restrict__ plan_parts2, int e, int lane,
+                                               double* __restrict__ fitness, int32_t* __restrict__ argmax) {
   const int status = ev.status;
   if (status != 1) {
     if (lane == 0) {
@@ -506,6 +492,83 @@ __global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ e
     fitness[e] = (double)g;
     argmax[e] = j;
   }
+}
+
+// The same by a group of 8 lanes (lane g of the group, groups aligned to 8
+// lanes, every lane of the group calling it): the largest (g, then smallest j)
+// of the partials is unique, so any grouping of the reduction gives the same
+// result as finalize_point.
+template <typename Real>
+__device__ __forceinline__ void finalize_group(const EvalDesc& ev, const Real* __restrict__ part_g,
+                                               const int32_t* __restrict__ part_j, int part_stride,
+                                               const int32_t* __restrict__ plan_parts2, int e, int g,
+                                               double* __restrict__ fitness, int32_t* __restrict__ argmax) {
+  const int status = ev.status;
+  if (status != 1) {
+    if (g == 0) {
+      fitness[e] = status == 0 ? -INFINITY : NAN;
+      argmax[e] = status == 0 ? -1 : -2;
+    }
+    return;
+  }
+  const int nt = plan_parts2[ev.plan];
+  Real bg = (Real)-1;
+  int bj = 0x7fffffff;
+  // batches of 16 loads per lane in flight before any is compared
+  constexpr int B = 16;
+  for (int t0 = g; t0 < nt; t0 += 8 * B) {
+    Real gv[B];
+    int jv[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int t = t0 + 8 * u;
+      gv[u] = t < nt ? part_g[(int64_t)e * part_stride + t] : (Real)-1;
+      jv[u] = t < nt ? part_j[(int64_t)e * part_stride + t] : 0x7fffffff;
+    }
+#pragma unroll
+    for (int u = 0; u < B; ++u)
+      if (better(gv[u], jv[u], bg, bj)) {
+        bg = gv[u];
+        bj = jv[u];
+      }
+  }
+#pragma unroll
+  for (int off = 4; off > 0; off >>= 1) {
+    const Real go = __shfl_xor(bg, off, 8);
+    const int jo = __shfl_xor(bj, off, 8);
+    if (better(go, jo, bg, bj)) {
+      bg = go;
+      bj = jo;
+    }
+  }
+  if (g == 0) {
+    fitness[e] = (double)bg;
+    argmax[e] = bj;
+  }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) k_finalize(const EvalDesc* __restrict__ evals,
+                                                  const SegDesc* __restrict__ segs, const Real* __restrict__ part_g,
+                                                  const int32_t* __restrict__ part_j, int n, int part_stride,
+                                                  const int32_t* __restrict__ plan_parts2,
+                                                  int32_t* __restrict__ counts,
+                                                  unsigned long long* __restrict__ evaluated,
+                                                  double* __restrict__ fitness, int32_t* __restrict__ argmax) {
+  const int lane = threadIdx.x & 63;
+  const int e = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    // running total of points evaluated (inside the rectangle); the passes of
+    // this call are done with the list counts, which start the next call at 0
+    unsigned long long t = 0;
+    for (int p = 0; p < kNumPlans; ++p) {
+      t += (unsigned long long)counts[p];
+      counts[p] = 0;
+    }
+    atomicAdd(evaluated, t);
+  }
+  if (e >= n) return;
+  finalize_point<Real>(evals[e], part_g, part_j, part_stride, plan_parts2, e, lane, fitness, argmax);
 }
 
 }  // namespace fcas

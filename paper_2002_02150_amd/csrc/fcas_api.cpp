@@ -86,6 +86,8 @@ struct fcas_ctx {
   EvalDesc* d_evals = nullptr;
   int32_t* d_lists = nullptr;    // [kNumPlans][max_batch]
   int32_t* d_counts = nullptr;   // [kNumPlans]
+  int32_t* d_lists2 = nullptr;   // second work-list set of pso_run (iterations alternate between the two)
+  int32_t* d_counts2 = nullptr;
   void* d_part_g = nullptr;      // [max_batch][part_stride]
   int32_t* d_part_j = nullptr;
   int32_t* d_plan_parts2 = nullptr;
@@ -182,7 +184,7 @@ int free_all(fcas_ctx* c) {
   void* bufs[] = {c->d_net, c->d_segs, c->d_evals, c->d_lists, c->d_counts, c->d_part_g,
                   c->d_part_j, c->d_plan_parts2, c->d_err, c->d_sigma2, c->d_inject, c->d_ws,
                   c->d_pol_grad, c->d_pol_cand, c->d_pol_seg, c->d_pol_f, c->d_pol_j, c->d_evaluated,
-                  c->d_done};
+                  c->d_done, c->d_lists2, c->d_counts2};
   for (void* p : bufs) if (p) hipFree(p);
   free_grad_buffers(c->grad);
   for (auto& t : c->t_pass1) { hipEventDestroy(t.a); hipEventDestroy(t.b); }
@@ -298,6 +300,8 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
       (rc = dev_alloc(&c->d_evals, sizeof(EvalDesc) * B)) ||
       (rc = dev_alloc(&c->d_lists, sizeof(int32_t) * (size_t)kNumPlans * B)) ||
       (rc = dev_alloc(&c->d_counts, sizeof(int32_t) * kNumPlans)) ||
+      (rc = dev_alloc(&c->d_lists2, sizeof(int32_t) * (size_t)kNumPlans * B)) ||
+      (rc = dev_alloc(&c->d_counts2, sizeof(int32_t) * kNumPlans)) ||
       (rc = dev_alloc(&c->d_part_g, part_elt * (size_t)B * c->part_stride)) ||
       (rc = dev_alloc(&c->d_part_j, sizeof(int32_t) * (size_t)B * c->part_stride)) ||
       (rc = dev_alloc(&c->d_plan_parts2, sizeof(int32_t) * kNumPlans)) ||
@@ -331,7 +335,8 @@ int fcas_create(const fcas_network* net, const fcas_config* cfg, int device, fca
       (e = hipMemcpy(c->d_plan_parts2, parts2, sizeof parts2, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemset(c->d_err, 0, sizeof(int32_t))) != hipSuccess ||
       (e = hipMemset(c->d_evaluated, 0, sizeof(unsigned long long))) != hipSuccess ||
-      (e = hipMemset(c->d_counts, 0, sizeof(int32_t) * kNumPlans)) != hipSuccess) {
+      (e = hipMemset(c->d_counts, 0, sizeof(int32_t) * kNumPlans)) != hipSuccess ||
+      (e = hipMemset(c->d_counts2, 0, sizeof(int32_t) * kNumPlans)) != hipSuccess) {
     rc = hip_fail(e, "context initialisation");
     free_all(c);
     delete c;
@@ -571,7 +576,7 @@ int enqueue_fused(fcas_ctx* ctx, const EvalBufs& b, int plan, int n, int cap, hi
 }
 
 int enqueue_passes(fcas_ctx* ctx, const EvalBufs& b, int32_t n, double* d_fitness, int32_t* d_argmax,
-                   hipStream_t s, bool fused_ok, bool timed);
+                   hipStream_t s, bool fused_ok, bool timed, bool finalize = true);
 
 // Enqueues set-up, the FFT passes of every plan in use, and finalize.
 int enqueue_eval(fcas_ctx* ctx, const EvalBufs& b, int32_t n, const double* d_theta, const int32_t* d_seg,
@@ -591,13 +596,13 @@ int enqueue_eval(fcas_ctx* ctx, int32_t n, const double* d_theta, const int32_t*
   return enqueue_eval(ctx, own_bufs(ctx), n, d_theta, d_seg, d_fitness, d_argmax, s);
 }
 
-// The FFT passes of every plan in use, then finalize (which clears the
-// work-list counts).  Plans with a middle pass, or with passes of unequal work
-// items, always run as separate launches (the fused schedule covers the other
-// two-pass plans, when fused_ok).  With `timed` false no timing events are
-// recorded whatever the context's setting.
+// The FFT passes of every plan in use, then (finalize) the finalize kernel,
+// which clears the work-list counts.  Plans with a middle pass, or with passes
+// of unequal work items, always run as separate launches (the fused schedule
+// covers the other two-pass plans, when fused_ok).  With `timed` false no
+// timing events are recorded whatever the context's setting.
 int enqueue_passes(fcas_ctx* ctx, const EvalBufs& b, int32_t n, double* d_fitness, int32_t* d_argmax,
-                   hipStream_t s, bool fused_ok, bool timed) {
+                   hipStream_t s, bool fused_ok, bool timed, bool finalize) {
   hipError_t e;
   int rc;
   const bool fused = fused_ok && ctx->schedule == FCAS_SCHEDULE_FUSED;
@@ -638,6 +643,7 @@ int enqueue_passes(fcas_ctx* ctx, const EvalBufs& b, int32_t n, double* d_fitnes
     }
   }
   ctx->timing = was_timing;
+  if (!finalize) return FCAS_OK;
   if ((e = launch_finalize(ctx->prec, b.evals, ctx->d_segs, b.part_g, b.part_j, n, ctx->part_stride,
                            ctx->d_plan_parts2, b.counts, ctx->d_evaluated, d_fitness, d_argmax, s)) != hipSuccess)
     return hip_fail(e, "finalize launch");
@@ -919,6 +925,76 @@ int pso_step(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, c
   hipSetDevice(ctx->device);
   hipError_t e = launch_pso_step(d, d_fitness, d_argmax, d_theta_next, (hipStream_t)hip_stream);
   return e == hipSuccess ? FCAS_OK : hip_fail(e, "pso_step launch");
+}
+
+int pso_run(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, int32_t n_iter, double* d_theta,
+            const int32_t* d_seg, double* d_fitness, int32_t* d_argmax, void* hip_stream) {
+  PsoDev d{};
+  int rc = make_pso(ctx, p, s, &d);
+  if (rc) return rc;
+  if (n_iter < 0) return fail(FCAS_EINVAL, "n_iter must be >= 0, got %d", n_iter);
+  const int64_t n64 = (int64_t)d.n_runs * d.n_particles;
+  if (n64 > ctx->cfg.max_batch)
+    return fail(FCAS_ECAPACITY, "n_runs * n_particles = %lld exceeds max_batch = %d", (long long)n64,
+                ctx->cfg.max_batch);
+  const int n = (int)n64;
+  if ((rc = validate_batch(ctx, n, d_theta, d_seg, d_fitness, d_argmax))) return rc;
+  if (n_iter == 0) return FCAS_OK;
+  hipSetDevice(ctx->device);
+  hipStream_t st = (hipStream_t)hip_stream;
+  hipError_t e;
+  if (d.n_particles > kTailMaxParticles) {
+    // runs too large for one work-group of the fused tail: separate launches
+    for (int it = 0; it < n_iter; ++it) {
+      if ((rc = enqueue_eval(ctx, own_bufs(ctx), n, d_theta, d_seg, d_fitness, d_argmax, st, true, false)))
+        return rc;
+      if ((e = launch_pso_step(d, d_fitness, d_argmax, d_theta, st)) != hipSuccess)
+        return hip_fail(e, "pso_step launch");
+    }
+    return FCAS_OK;
+  }
+  // Iteration it evaluates from work-list set it % 2; the tail kernel that
+  // ends it clears that set's counts and appends the next points to the other.
+  EvalBufs b[2] = {own_bufs(ctx), own_bufs(ctx)};
+  b[1].lists = ctx->d_lists2;
+  b[1].counts = ctx->d_counts2;
+  auto clear_counts = [&]() {
+    launch_zero_i32(b[0].counts, kNumPlans, st);
+    launch_zero_i32(b[1].counts, kNumPlans, st);
+  };
+  if ((rc = enqueue_setup(ctx, b[0], n, d_theta, d_seg, st))) return rc;
+  for (int it = 0; it < n_iter; ++it) {
+    const EvalBufs& cur = b[it & 1];
+    const EvalBufs& nxt = b[(it + 1) & 1];
+    if ((rc = enqueue_passes(ctx, cur, n, d_fitness, d_argmax, st, true, false, false))) {
+      clear_counts();
+      return rc;
+    }
+    TailArgs t{};
+    t.net = ctx->d_net;
+    t.segs = ctx->d_segs;
+    t.evals = cur.evals;
+    t.part_g = cur.part_g;
+    t.part_j = cur.part_j;
+    t.part_stride = ctx->part_stride;
+    t.list_stride = nxt.list_stride;
+    t.plan_parts2 = ctx->d_plan_parts2;
+    t.counts_cur = cur.counts;
+    t.lists_next = nxt.lists;
+    t.counts_next = nxt.counts;
+    t.evaluated = ctx->d_evaluated;
+    t.fitness = d_fitness;
+    t.argmax = d_argmax;
+    t.theta = d_theta;
+    t.seg_ids = d_seg;
+    t.err = ctx->d_err;
+    t.setup = it + 1 < n_iter ? 1 : 0;
+    if ((e = launch_pso_tail(ctx->prec, d, t, st)) != hipSuccess) {
+      clear_counts();
+      return hip_fail(e, "PSO tail launch");
+    }
+  }
+  return FCAS_OK;
 }
 
 int pso_best(fcas_ctx* ctx, const fcas_pso_params* p, const fcas_pso_state* s, double* d_out_f,

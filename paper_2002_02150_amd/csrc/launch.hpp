@@ -64,6 +64,35 @@ int fused_occupancy_plan() {
   return nb;
 }
 
+// The end of one PSO iteration in one launch (tail.hip): finalize of every
+// point, the swarm update, and (setup) the set-up of the next positions with
+// their entries in the other work-list set.  Up to kTailMaxParticles
+// particles per run (8 lanes each).
+constexpr int kTailMaxParticles = 128;
+constexpr int kTailMaxThreads = 8 * kTailMaxParticles;
+struct TailArgs {
+  const NetDesc* net;
+  const SegDesc* segs;
+  EvalDesc* evals;
+  const void* part_g;
+  const int32_t* part_j;
+  int32_t part_stride;
+  int32_t list_stride;
+  const int32_t* plan_parts2;
+  int32_t* counts_cur;           // list counts of the iteration just evaluated (cleared here)
+  int32_t* lists_next;           // work lists of the next iteration, [kNumPlans][list_stride]
+  int32_t* counts_next;          // their counts (zero on entry)
+  unsigned long long* evaluated;
+  double* fitness;
+  int32_t* argmax;
+  double* theta;                 // written by the update (next points), then read by the set-up
+  const int32_t* seg_ids;
+  int32_t* err;
+  int32_t setup;                 // 0: last iteration, no set-up
+};
+struct PsoDev;
+hipError_t launch_pso_tail(int precision, const PsoDev& p, const TailArgs& t, hipStream_t s);
+
 // segment preparation: sigma_i^2 = 4 df sum_B f^-7/3 / S, y = 4 df x f^-7/6 / (S sigma), b = (f/f*)^-1/3
 hipError_t launch_segment_sigma(const double* psd, int n_det, int64_t half, int k_lo, int k_hi, double df,
                                 double* sigma2_out, hipStream_t s);

@@ -28,7 +28,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOSEG", -3: "EUNSUPPORTED_N", -4: "EHIP",
 EXPORTED = ("fcas_create", "fcas_destroy", "fcas_workspace_bytes", "fcas_supported_n", "fcas_plan_count",
             "fcas_plan_info", "fcas_select_plan", "fcas_set_segment", "fcas_set_segment_range",
             "fitness_eval_batch", "fitness_eval_batch_static", "fitness_grad_batch", "fitness_polish", "pso_init",
-            "pso_step", "pso_best", "pso_best_segments",
+            "pso_step", "pso_run", "pso_best", "pso_best_segments",
             "fcas_inject", "fcas_evaluated", "fcas_device_error", "fcas_set_timing", "fcas_read_timing", "fcas_last_error")
 
 
@@ -91,6 +91,8 @@ def library():
         "fitness_polish": ([vp, i32, vp, vp, i32, ctypes.c_double, i32, vp, vp, vp], ctypes.c_int),
         "pso_init": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp], ctypes.c_int),
         "pso_step": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, vp, vp], ctypes.c_int),
+        "pso_run": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), i32, vp, vp, vp, vp, vp],
+                    ctypes.c_int),
         "pso_best": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), vp, vp, vp, vp, vp], ctypes.c_int),
         "pso_best_segments": ([vp, ctypes.POINTER(_PsoParams), ctypes.POINTER(_PsoState), i32, i32, vp, vp, vp, vp,
                                vp], ctypes.c_int),
@@ -363,6 +365,17 @@ class Swarm:
         _want(argmax, torch.int32, (self.n,), self.ctx.device, "argmax")
         _check(library().pso_step(self.ctx._h, ctypes.byref(self._p), ctypes.byref(self._s), _ptr(fitness),
                                   _ptr(argmax), _ptr(self.theta), _stream(self.ctx.device)))
+        return self.theta
+
+    def run(self, n_iter, seg, fitness, argmax):
+        """pso_run: n_iter iterations (fitness of the current points, then the
+        swarm update) on self.theta; fitness / argmax receive the last
+        iteration's values."""
+        _want(seg, torch.int32, (self.n,), self.ctx.device, "seg")
+        _want(fitness, torch.float64, (self.n,), self.ctx.device, "fitness")
+        _want(argmax, torch.int32, (self.n,), self.ctx.device, "argmax")
+        _check(library().pso_run(self.ctx._h, ctypes.byref(self._p), ctypes.byref(self._s), int(n_iter),
+                                 _ptr(self.theta), _ptr(seg), _ptr(fitness), _ptr(argmax), _stream(self.ctx.device)))
         return self.theta
 
     def best_segments(self, runs_per_segment, runs_used=None):

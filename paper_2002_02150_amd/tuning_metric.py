@@ -55,25 +55,19 @@ def search(ctx, n_seg, cfg: PsoConfig, group=20):
     j = torch.empty(n, dtype=torch.int32, device=dev)
     sw.init()
 
-    def iteration():
-        ctx.eval(sw.theta, seg, f, j)
-        sw.step(f, j)
-
     st = torch.cuda.Stream(dev)
     st.wait_stream(torch.cuda.current_stream(dev))
     with torch.cuda.stream(st):
-        iteration()
+        sw.run(1, seg, f, j)          # iteration 1, eagerly, before the capture
     torch.cuda.current_stream(dev).wait_stream(st)
     group = max(1, min(group, cfg.n_iter - 1))
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g):
-        for _ in range(group):
-            iteration()
+        sw.run(group, seg, f, j)      # `group` iterations: fitness, then swarm update
     rest = cfg.n_iter - 1
     for _ in range(rest // group):
         g.replay()
-    for _ in range(rest % group):
-        iteration()
+    sw.run(rest % group, seg, f, j)
     return sw
 
 
