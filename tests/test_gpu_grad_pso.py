@@ -13,7 +13,7 @@ from tests._gpu import dev, make_ctx, require_gpu, upload
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("prec,tol,rtol", [(0, 2e-4, 1e-2), (1, 1e-8, 1e-7)], ids=["mixed", "fp64"])
+@pytest.mark.parametrize("prec,tol,rtol", [(0, 1e-5, 1e-4), (1, 1e-10, 1e-9)], ids=["mixed", "fp64"])
 def test_gradient_matches_oracle(prec, tol, rtol):
     """dGamma^2/dtheta at the GPU's maximising sample vs the oracle's analytic
     gradient at the same sample (itself pinned to finite differences): every
@@ -29,6 +29,7 @@ def test_gradient_matches_oracle(prec, tol, rtol):
     f, j, g = ctx.grad(torch.from_numpy(th).to(dev()), torch.zeros(len(th), dtype=torch.int32, device=dev()))
     f, j, g = f.cpu().numpy(), j.cpu().numpy(), g.cpu().numpy()
     w = np.array(hi) - np.array(lo)
+    worst_abs = worst_rel = 0.0
     for k in range(len(th)):
         g2, _, go = G.fitness_gradient(case.seg, case.net.pos_m, case.net.tensor, th[k], int(j[k]))
         scale = np.max(np.abs(go * w))     # gradient scale in box-width units
@@ -36,6 +37,9 @@ def test_gradient_matches_oracle(prec, tol, rtol):
         assert np.all(err <= tol * scale), (k, g[k], go)
         big = np.abs(go * w) > 1e-3 * scale
         assert np.all(err[big] <= rtol * np.abs(go * w)[big]), (k, g[k], go)
+        worst_abs = max(worst_abs, float(np.max(err) / scale))
+        worst_rel = max(worst_rel, float(np.max(err[big] / np.abs(go * w)[big])))
+    print(f"gradient 16384 prec={prec}: max |dg w|/s {worst_abs:.3e}, max per-component rel {worst_rel:.3e}")
     ctx.close()
 
 

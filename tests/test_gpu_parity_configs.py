@@ -101,7 +101,7 @@ def test_ragged_config3_lengths_one_call():
     ctx.close()
 
 
-@pytest.mark.parametrize("prec,rtol,atol", [(0, 1e-2, 2e-4), (1, 1e-7, 1e-9)], ids=["mixed", "fp64"])
+@pytest.mark.parametrize("prec,rtol,atol", [(0, 1e-4, 1e-5), (1, 1e-9, 1e-9)], ids=["mixed", "fp64"])
 def test_gradient_131072_per_component(prec, rtol, atol):
     """dGamma^2/dtheta at 4 x 131072 samples for 16 points within 1% of the
     rectangle width of an SNR-12 source, against the oracle's analytic
@@ -109,9 +109,10 @@ def test_gradient_131072_per_component(prec, rtol, atol):
     s = max_q |g_q w_q|, every component satisfies |dg_q w_q| <= atol s, and
     every component with |g_q w_q| > 1e-3 s is also within rtol of itself.
 
-    Mixed path: the sums over the 62,080 bins are FP32, so an error of a few
-    1e-7 of the sum of the terms' magnitudes, which is at most the scale s,
-    becomes up to ~1e-3 of a component 1e-3 of s: rtol 1e-2 covers it."""
+    Mixed path: the sums over the 62,080 bins are FP32, an error of a few
+    1e-7 of the sum of the terms' magnitudes; measured 4.9e-7 of s at worst
+    and 1.7e-6 of a component (FP64: 4.4e-11), so the bars hold the measured
+    errors with a margin of 20 or more."""
     require_gpu()
     case = Case("HLVK", 131072, 2048.0, snr=12.0, cfg=4, realization=0)
     lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
