@@ -108,17 +108,20 @@ FCAS_HD void setup_point(const NetDesc& net, const double* th, double coef[4], S
   fr.ey[0] = -sd * ca; fr.ey[1] = -sd * sa; fr.ey[2] = cd;
 }
 
-// Delay ramp of detector i in cycles per bin (delay relative to the geocentre).
-FCAS_HD double detector_delay(const NetDesc& net, const SegDesc& sg, const SkyFrame& fr, int i) {
+// Delay ramp of detector i in cycles per bin of width df (delay relative to
+// the geocentre).
+FCAS_HD double detector_delay(const NetDesc& net, double df, const SkyFrame& fr, int i) {
   const double* r = net.pos[i];
-  return -(fr.n[0] * r[0] + fr.n[1] * r[1] + fr.n[2] * r[2]) / kC * sg.df;
+  return -(fr.n[0] * r[0] + fr.n[1] * r[1] + fr.n[2] * r[2]) / kC * df;
 }
 
-// Detector i: delay ramp (cycles per bin), its pass-1 step relative to
-// detector 0, and row i of V.
-FCAS_HD void setup_detector(const NetDesc& net, const SegDesc& sg, const SkyFrame& fr, int i, EvalDesc& ev) {
-  ev.dly[i] = detector_delay(net, sg, fr, i);
-  const double ps = (double)sg.dk1 * (ev.dly[i] - detector_delay(net, sg, fr, 0));
+// Detector i of a segment with bin width df, pass-1 register stride dk1 and
+// template norm sigma_i: delay ramp (cycles per bin), its pass-1 step
+// relative to detector 0, and row i of V.
+FCAS_HD void setup_detector(const NetDesc& net, double df, int dk1, double sigma_i, const SkyFrame& fr, int i,
+                            EvalDesc& ev) {
+  ev.dly[i] = detector_delay(net, df, fr, i);
+  const double ps = (double)dk1 * (ev.dly[i] - detector_delay(net, df, fr, 0));
   double ss, cs;
   sincos_rev(ps - rint(ps), &ss, &cs);
   ev.step1[i][0] = cs;
@@ -132,8 +135,8 @@ FCAS_HD void setup_detector(const NetDesc& net, const SegDesc& sg, const SkyFram
       up += d * (fr.ex[a] * fr.ex[b] - fr.ey[a] * fr.ey[b]);
       uc += d * (fr.ex[a] * fr.ey[b] + fr.ey[a] * fr.ex[b]);
     }
-  ev.v[i][0] = sg.sigma[i] * up;
-  ev.v[i][1] = sg.sigma[i] * uc;
+  ev.v[i][0] = sigma_i * up;
+  ev.v[i][1] = sigma_i * uc;
 }
 
 // Orthonormal basis Q of span(V): modified Gram-Schmidt, twice, larger
@@ -192,7 +195,7 @@ struct DetLoop {
 FCAS_HD void setup_one(const NetDesc& net, const SegDesc& sg, const double* th, EvalDesc& ev) {
   SkyFrame fr;
   setup_point(net, th, ev.coef, fr);
-  for (int i = 0; i < net.n_det; ++i) setup_detector(net, sg, fr, i, ev);
+  for (int i = 0; i < net.n_det; ++i) setup_detector(net, sg.df, sg.dk1, sg.sigma[i], fr, i, ev);
   ev.rank = setup_basis(ev, DetLoop{net.n_det});
 }
 

@@ -43,8 +43,11 @@ __global__ void k_pso_init(PsoDev p, double* __restrict__ theta) {
 
 __global__ void k_pso_step(PsoDev p, const double* __restrict__ fitness, const int32_t* __restrict__ argmax,
                            double* __restrict__ theta) {
-  extern __shared__ double pf[];   // personal-best fitness of the run's particles
-  pso_step_run(p, fitness, argmax, theta, pf, blockIdx.x, threadIdx.x);
+  extern __shared__ double sm[];   // PsoShared: pf[P], px[P][4], then pj[P]
+  const int P = p.n_particles;
+  const PsoShared sh{sm, sm + P, (int32_t*)(sm + 5 * P)};
+  PsoLocal L = pso_load(p, blockIdx.x, threadIdx.x);
+  pso_step_run(p, L, fitness, argmax, theta, sh, nullptr, blockIdx.x, threadIdx.x);
 }
 
 // Best of the first u runs of each group of m consecutive runs (one group per
@@ -75,7 +78,7 @@ hipError_t launch_pso_init(const PsoDev& p, double* theta_out, hipStream_t s) {
 hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, double* theta_next,
                            hipStream_t s) {
   hipLaunchKernelGGL(k_pso_step, dim3(p.n_runs), dim3(block_for(p.n_particles)),
-                     sizeof(double) * p.n_particles, s, p, fitness, argmax, theta_next);
+                     pso_shared_bytes(p.n_particles), s, p, fitness, argmax, theta_next);
   return hipGetLastError();
 }
 

@@ -53,29 +53,70 @@ __device__ __forceinline__ double clampv(double v, double vmax) {
   return v > vmax ? vmax : v;
 }
 
-// One iteration of run r (Sec. III), thread i of the run's work-group: every
-// thread of the work-group calls it (threads i >= P only synchronise); pf
-// holds P doubles of LDS.  Given the fitness and argmax of the current
+// A particle's swarm state as its iteration begins (read before its fitness
+// is known), and the iteration count and its run's best fitness.
+struct PsoLocal {
+  double x[4], v[4], pbx[4];
+  double pb;
+  int32_t pbj;
+  int32_t iter;
+  double run_best;
+};
+
+__device__ __forceinline__ PsoLocal pso_load(const PsoDev& p, int r, int i) {
+  PsoLocal L{};
+  L.iter = p.iteration[0];
+  L.run_best = p.best_f[r];
+  if (i < p.n_particles) {
+    const int64_t o = (int64_t)r * p.n_particles + i;
+    for (int d = 0; d < 4; ++d) {
+      L.x[d] = p.x[4 * o + d];
+      L.v[d] = p.v[4 * o + d];
+      L.pbx[d] = p.pbest_x[4 * o + d];
+    }
+    L.pb = p.pbest_f[o];
+    L.pbj = p.pbest_j[o];
+  }
+  return L;
+}
+
+// LDS of one run's update: personal-best fitness pf[P], positions px[P][4]
+// and samples pj[P] after this iteration's personal-best update.
+struct PsoShared {
+  double* pf;
+  double* px;
+  int32_t* pj;
+};
+
+// One iteration of run r (Sec. III), thread i of the run's work-group, from
+// the state pso_load read: every thread of the work-group calls it (threads
+// i >= P only synchronise).  Given the fitness and argmax of the current
 // positions: personal, local and run bests, the move, and theta of the next
-// positions.  The last run to finish advances the iteration count.
-__device__ __forceinline__ void pso_step_run(const PsoDev& p, const double* __restrict__ fitness,
+// positions (also to theta_lds[P][4] when not null).  The last run to finish
+// advances the iteration count.
+__device__ __forceinline__ void pso_step_run(const PsoDev& p, PsoLocal& L, const double* __restrict__ fitness,
                                              const int32_t* __restrict__ argmax, double* __restrict__ theta,
-                                             double* pf, int r, int i) {
+                                             PsoShared sh, double* theta_lds, int r, int i) {
 #pragma clang fp contract(off)
   const int P = p.n_particles;
-  const int iter = p.iteration[0];
+  const int iter = L.iter;
   const int64_t base = (int64_t)r * P;
   if (i < P) {
     const int64_t o = base + i;
-    double pb = p.pbest_f[o];
     const double f = fitness[o];
-    if (f > pb) {
-      pb = f;
+    if (f > L.pb) {
+      L.pb = f;
+      L.pbj = argmax[o];
       p.pbest_f[o] = f;
-      p.pbest_j[o] = argmax[o];
-      for (int d = 0; d < 4; ++d) p.pbest_x[4 * o + d] = p.x[4 * o + d];
+      p.pbest_j[o] = L.pbj;
+      for (int d = 0; d < 4; ++d) {
+        L.pbx[d] = L.x[d];
+        p.pbest_x[4 * o + d] = L.x[d];
+      }
     }
-    pf[i] = pb;
+    sh.pf[i] = L.pb;
+    sh.pj[i] = L.pbj;
+    for (int d = 0; d < 4; ++d) sh.px[4 * i + d] = L.pbx[d];
   }
   __syncthreads();
   if (i < 64) {
@@ -85,8 +126,8 @@ __device__ __forceinline__ void pso_step_run(const PsoDev& p, const double* __re
     double bv = -INFINITY;
     int b = 0x7fffffff;
     for (int k = i; k < P; k += 64)
-      if (b == 0x7fffffff || pf[k] > bv) {
-        bv = pf[k];
+      if (b == 0x7fffffff || sh.pf[k] > bv) {
+        bv = sh.pf[k];
         b = k;
       }
 #pragma unroll
@@ -98,32 +139,34 @@ __device__ __forceinline__ void pso_step_run(const PsoDev& p, const double* __re
         b = ob;
       }
     }
-    if (i == 0 && pf[b] > p.best_f[r]) {
-      p.best_f[r] = pf[b];
-      p.best_j[r] = p.pbest_j[base + b];
-      for (int d = 0; d < 4; ++d) p.best_x[4 * r + d] = p.pbest_x[4 * (base + b) + d];
+    if (i == 0 && sh.pf[b] > L.run_best) {
+      p.best_f[r] = sh.pf[b];
+      p.best_j[r] = sh.pj[b];
+      for (int d = 0; d < 4; ++d) p.best_x[4 * r + d] = sh.px[4 * b + d];
     }
   }
   if (i < P) {
     const int cand[3] = {(i + P - 1) % P, i, (i + 1) % P};
     int lb = cand[0];
     for (int c = 1; c < 3; ++c)
-      if (pf[cand[c]] > pf[lb]) lb = cand[c];
+      if (sh.pf[cand[c]] > sh.pf[lb]) lb = cand[c];
     const double w = p.n_iter <= 1 ? p.w0 : p.w0 - (p.w0 - p.w1) * ((double)iter / (double)(p.n_iter - 1));
     double r1[4], r2[4];
     uniforms4(p.seed, (uint32_t)(iter + 1), i, r, 2, r1);
     uniforms4(p.seed, (uint32_t)(iter + 1), i, r, 3, r2);
-    const int64_t o = base + i, ol = base + lb;
+    const int64_t o = base + i;
     for (int d = 0; d < 4; ++d) {
-      const double xv = p.x[4 * o + d];
-      const double t0 = w * p.v[4 * o + d];
-      const double t1 = (p.c1 * r1[d]) * (p.pbest_x[4 * o + d] - xv);
-      const double t2 = (p.c2 * r2[d]) * (p.pbest_x[4 * ol + d] - xv);
+      const double xv = L.x[d];
+      const double t0 = w * L.v[d];
+      const double t1 = (p.c1 * r1[d]) * (L.pbx[d] - xv);
+      const double t2 = (p.c2 * r2[d]) * (sh.px[4 * lb + d] - xv);
       const double vn = clampv((t0 + t1) + t2, p.vmax);
       const double xn = xv + vn;
       p.v[4 * o + d] = vn;
       p.x[4 * o + d] = xn;
-      theta[4 * o + d] = p.lo[d] + xn * p.span[d];
+      const double th = p.lo[d] + xn * p.span[d];
+      theta[4 * o + d] = th;
+      if (theta_lds) theta_lds[4 * i + d] = th;
     }
   }
   // The iteration count advances once every run has read it: each run's
@@ -138,6 +181,9 @@ __device__ __forceinline__ void pso_step_run(const PsoDev& p, const double* __re
     }
   }
 }
+
+// LDS bytes of one run's update (PsoShared) for P particles.
+constexpr size_t pso_shared_bytes(int P) { return (size_t)P * (sizeof(double) * 5 + sizeof(int32_t)); }
 
 hipError_t launch_pso_init(const PsoDev& p, double* theta_out, hipStream_t s);
 hipError_t launch_pso_step(const PsoDev& p, const double* fitness, const int32_t* argmax, double* theta_next,

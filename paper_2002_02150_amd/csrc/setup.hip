@@ -17,7 +17,10 @@ __global__ void __launch_bounds__(64) k_setup(const NetDesc* __restrict__ netp, 
                                               int32_t* __restrict__ counts, int list_stride, int build_lists,
                                               int32_t* __restrict__ err) {
   const int e = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 3);
-  setup_group(*netp, segs, theta, seg_ids, e, e < n, evals, lists, counts, list_stride, build_lists, err);
+  const NetDesc& net = *netp;
+  const SetupSeg q = setup_seg_load(net, segs, seg_ids, e, e < n);
+  setup_group(net, q, theta + 4 * (int64_t)(e < n ? e : 0), e, e < n, evals, lists, counts, list_stride, build_lists,
+              err);
 }
 
 // sigma_i^2 = 4 df sum_{k in B} f_k^(-7/3) / S^i_k  (template norm, Sec. II.D).

@@ -27,31 +27,52 @@ struct DetLanes {
 };
 static_assert(kMaxDet == 8, "one lane per detector slot in a group of 8");
 
-// Set-up of point e (valid) by the 8-lane group holding it: status, the FP64
-// set-up with the per-detector work spread over the lanes, and (build_lists)
-// the append to its plan's work list.  Every lane of the wavefront calls it,
-// lanes without a point with valid = false: list entries of one wavefront that
-// share a plan are appended with a single atomic.
-__device__ __forceinline__ void setup_group(const NetDesc& net, const SegDesc* __restrict__ segs,
-                                            const double* __restrict__ theta, const int32_t* __restrict__ seg_ids,
-                                            int e, bool valid, EvalDesc* __restrict__ evals,
-                                            int32_t* __restrict__ lists, int32_t* __restrict__ counts,
-                                            int list_stride, int build_lists, int32_t* __restrict__ err) {
+// What the set-up of one point reads of its segment: the segment id, whether
+// it can be evaluated, and the segment's plan, bin width, pass-1 register
+// stride and (lane g) detector g's template norm.
+struct SetupSeg {
+  int32_t s, ok, plan, dk1;
+  double df, sigma_g;
+};
+
+__device__ __forceinline__ SetupSeg setup_seg_load(const NetDesc& net, const SegDesc* __restrict__ segs,
+                                                   const int32_t* __restrict__ seg_ids, int e, bool valid) {
+  SetupSeg q{};
+  if (!valid) return q;
+  q.s = seg_ids[e];
+  if (q.s < 0 || q.s >= net.max_segments) return q;
+  const SegDesc& sg = segs[q.s];
+  q.ok = sg.registered;
+  q.plan = sg.plan;
+  q.dk1 = sg.dk1;
+  q.df = sg.df;
+  const int g = threadIdx.x & 7;
+  q.sigma_g = g < net.n_det ? sg.sigma[g] : 0.0;
+  return q;
+}
+
+// Set-up of point e (valid) by the 8-lane group holding it, given its segment
+// (setup_seg_load) and its parameters th[4]: status, the FP64 set-up with the
+// per-detector work spread over the lanes, and (build_lists) the append to
+// its plan's work list.  Every lane of the wavefront calls it, lanes without
+// a point with valid = false: list entries of one wavefront that share a plan
+// are appended with a single atomic.
+__device__ __forceinline__ void setup_group(const NetDesc& net, const SetupSeg& q, const double* th, int e,
+                                            bool valid, EvalDesc* __restrict__ evals, int32_t* __restrict__ lists,
+                                            int32_t* __restrict__ counts, int list_stride, int build_lists,
+                                            int32_t* __restrict__ err) {
   const int lane = threadIdx.x & 63, g = threadIdx.x & 7;
   int plan = -1;   // on lane 0 of a group: plan of a point to append to its list, else -1
   if (valid) {
     EvalDesc& ev = evals[e];
-    const int s = seg_ids[e];
-    if (s < 0 || s >= net.max_segments || !segs[s].registered) {
+    if (!q.ok) {
       if (g == 0) {
-        ev.seg = s;
+        ev.seg = q.s;
         ev.status = -2;
         ev.plan = 0;
         atomicOr(err, 1);
       }
     } else {
-      const SegDesc& sg = segs[s];
-      const double* th = theta + 4 * (int64_t)e;
       bool inside = true;
       for (int d = 0; d < 4; ++d) {
         const double t = th[d];
@@ -61,17 +82,17 @@ __device__ __forceinline__ void setup_group(const NetDesc& net, const SegDesc* _
         double coef[4];
         SkyFrame fr;
         setup_point(net, th, coef, fr);
-        if (g < net.n_det) setup_detector(net, sg, fr, g, ev);
+        if (g < net.n_det) setup_detector(net, q.df, q.dk1, q.sigma_g, fr, g, ev);
         const int rank = setup_basis(ev, DetLanes{net.n_det, g});
         if (g == 0) {
           for (int k = 0; k < 4; ++k) ev.coef[k] = coef[k];
           ev.rank = rank;
-          if (build_lists) plan = sg.plan;
+          if (build_lists) plan = q.plan;
         }
       }
       if (g == 0) {
-        ev.seg = s;
-        ev.plan = sg.plan;
+        ev.seg = q.s;
+        ev.plan = q.plan;
         ev.status = inside ? 1 : 0;
       }
     }
