@@ -202,13 +202,17 @@ def run(slides=4, per_snr=64, snrs=(9.0, 10.0, 12.0, 15.0), iters=1000, runs=8, 
 HOUR = 7372800
 
 
-def hour_h0(first=1, last=24, iters=500, runs=12, group=8, seed=8, polish_steps=20, log=print):
-    """H0 values rho' of the time-slid hour-long noise-only segments first..last."""
+def hour_h0(first=1, last=24, iters=500, runs=12, group=8, seed=8, polish_steps=20, f_low=F_LOW, log=print):
+    """H0 values rho' of the time-slid hour-long noise-only segments first..last
+    (f_low = 10: the paper's band and rectangle, as hour_h1)."""
     import synth
     dev = torch.device("cuda", 0)
     net = synth.network("HLVK")
     D = net.n_det
-    lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
+    if f_low == PAPER_F_LOW:
+        lo, hi = PAPER_BOX_LO, PAPER_BOX_HI
+    else:
+        lo, hi = synth.SEARCH_BOX_30HZ_LO, synth.SEARCH_BOX_30HZ_HI
     series = np.stack([synth.td_noise(np.random.default_rng(synth.seed_sequence(seed, 0, i)), HOUR, FS)
                        for i in range(D)])
     psd = torch.from_numpy(synth.psd_matrix(D, HOUR, FS)).to(dev)
@@ -216,7 +220,7 @@ def hour_h0(first=1, last=24, iters=500, runs=12, group=8, seed=8, polish_steps=
     for g0 in range(first, last + 1, group):
         slides = list(range(g0, min(g0 + group, last + 1)))
         n = len(slides) * runs * 40
-        ctx = Context.from_network(net, fs=FS, f_low=F_LOW, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
+        ctx = Context.from_network(net, fs=FS, f_low=f_low, f_high=F_HIGH, box_lo=lo, box_hi=hi, max_batch=n,
                                    max_segments=len(slides), max_samples=HOUR,
                                    workspace_bytes=min(16 << 30, n * 2 * HOUR * 8))
         for k, s in enumerate(slides):
@@ -231,8 +235,8 @@ def hour_h0(first=1, last=24, iters=500, runs=12, group=8, seed=8, polish_steps=
             rho[s] = float(np.sqrt(max(res["rho_sq"][k].item(), 0.0)))
         ctx.close()
         log(f"slides {slides[0]}-{slides[-1]}: rho' " + " ".join(f"{rho[s]:.3f}" for s in slides))
-    return dict(segment_samples=HOUR, slides=[first, last], iterations=iters, runs=runs, seconds_search=seconds,
-                rho=rho)
+    return dict(segment_samples=HOUR, slides=[first, last], iterations=iters, runs=runs, f_low=f_low,
+                seconds_search=seconds, rho=rho)
 
 
 # The paper's own search rectangle and band (Sec. II.B, Sec. V): f_* = 10 Hz,
@@ -331,7 +335,13 @@ def h1_table(eta, outs):
 def combine(outs, far_per_year=1.0):
     """Lognormal fit of the H0 values of several hour_h0 runs and the threshold."""
     rho = {}
+    bands = {o.get("f_low", F_LOW) for o in outs}
+    if len(bands) > 1:
+        raise ValueError(f"H0 runs of different bands (f_low {sorted(bands)}) cannot share a threshold")
     for o in outs:
+        dup = sorted(set(rho) & {int(k) for k in o["rho"]})
+        if dup:
+            raise ValueError(f"slides {dup} appear in more than one output")
         rho.update({int(k): v for k, v in o["rho"].items()})
     vals = np.array([rho[k] for k in sorted(rho)])
     p_fa = far_per_year * HOUR / FS / YEAR_S
@@ -339,7 +349,8 @@ def combine(outs, far_per_year=1.0):
     return dict(segments_h0=len(vals), p_false_alarm_per_segment=p_fa, eta=eta,
                 h0_lognormal=dict(mu=mu, sigma=sd, ks_pvalue=ks_p),
                 h0_rho_quantiles={q: float(np.quantile(vals, q)) for q in (0.05, 0.5, 0.95, 1.0)},
-                iterations=sorted({o["iterations"] for o in outs}), runs=sorted({o["runs"] for o in outs}))
+                iterations=sorted({o["iterations"] for o in outs}), runs=sorted({o["runs"] for o in outs}),
+                f_low=bands.pop())
 
 
 def main(argv=None):
@@ -359,7 +370,7 @@ def main(argv=None):
                     help="H1 sources: paper (L4 and L5; default) or random for the 64-s study; random, L4 or L5 "
                          "with --hour-h1")
     ap.add_argument("--f-low", type=float, default=F_LOW,
-                    help="--hour-h1: 10 takes the paper's band and rectangle (f_* = 10 Hz, tau0 in [500, 1500] s, "
+                    help="--hour and --hour-h1: 10 takes the paper's band and rectangle (f_* = 10 Hz, tau0 in [500, 1500] s, "
                          "tau1.5 in [5, 15] s)")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
@@ -385,7 +396,7 @@ def main(argv=None):
         return 0
     if a.hour:
         first, last = (int(x) for x in str(a.slides).split("-"))
-        out = hour_h0(first, last, iters=a.iters or 500, runs=a.runs or 12, log=log)
+        out = hour_h0(first, last, iters=a.iters or 500, runs=a.runs or 12, f_low=a.f_low, log=log)
         print(json.dumps(out))
         return 0
     out = run(int(a.slides), a.per_snr, tuple(float(x) for x in a.snrs.split(",")), a.iters or 1000,

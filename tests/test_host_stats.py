@@ -110,3 +110,20 @@ def test_detection_rows_location_ks_test():
     assert row["ks_pvalue_locations"] == pytest.approx(_ks_perm_pvalue(a, b), rel=1e-9)
     assert row["ks_pvalue_locations_above_9"] == pytest.approx(_ks_perm_pvalue(a[1:], b[1:]), rel=1e-9)
     assert row["ks_pvalue_locations_above_9"] == pytest.approx(0.1)      # 2 of the 20 splits of 3 + 3 separate fully
+
+
+def test_hour_h0_combine_checks():
+    """The hour-long H0 outputs combine into one lognormal fit only when they
+    share a band and no slide appears twice."""
+    from paper_2002_02150_amd.detection import combine
+    rng = np.random.default_rng(3)
+    a = dict(rho={str(s): float(v) for s, v in zip(range(1, 9), rng.lognormal(2.1, 0.03, 8))}, iterations=500,
+             runs=12, f_low=10.0)
+    b = dict(rho={str(s): float(v) for s, v in zip(range(9, 17), rng.lognormal(2.1, 0.03, 8))}, iterations=500,
+             runs=12, f_low=10.0)
+    c = combine([a, b])
+    assert c["segments_h0"] == 16 and c["f_low"] == 10.0 and c["eta"] > max(max(a["rho"].values()), 8.0)
+    with pytest.raises(ValueError):
+        combine([a, a])
+    with pytest.raises(ValueError):
+        combine([a, dict(b, f_low=30.0)])
