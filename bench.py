@@ -9,8 +9,8 @@ second over the timed region (inputs resident in HBM; particles that left the
 search rectangle are not evaluated and not counted).  The best of the runs and
 the gradient polish of that point, done once per search, are timed on their
 own after the iterations (polish_ms).  A second
-timed region launches the same steps eagerly with HIP events around the FFT
-pass kernels, for the roofline figures.  The FP64 oracle evaluates the first
+timed region launches the same steps eagerly with HIP events recorded by the
+FFT pass kernels' dispatch, for the roofline figures.  The FP64 oracle evaluates the first
 PSO batch on the host cores (cpu_baseline), and the library's results on the
 same points are compared with it (parity: relative error of the fitness,
 argmax agreement).
@@ -485,7 +485,7 @@ def run_hour(a, torch, dev):
     search.polish()
     torch.cuda.synchronize()
     dt_polish = time.perf_counter() - tp
-    # eager steps with HIP events around the three FFT passes
+    # eager steps with HIP events recorded by the three FFT passes' dispatch
     eager = min(a.steps, 20)
     ev2 = ctx.evaluated()
     for _ in range(eager):
@@ -604,8 +604,8 @@ def main():
     torch.cuda.synchronize()
     dt_polish = time.perf_counter() - tp
     iterations_done = sw.iteration.item()
-    # timed region 2: K iterations launched eagerly, HIP events around the FFT
-    # passes
+    # timed region 2: K iterations launched eagerly, HIP events recorded by the
+    # FFT passes' dispatch
     ev2 = ctx.evaluated()
     t2 = time.perf_counter()
     per_launch = []

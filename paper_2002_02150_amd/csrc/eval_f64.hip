@@ -6,19 +6,19 @@ namespace fcas {
 #define FCAS_CASE_P1(id, ...)                                                                   \
   case id:                                                                                       \
     switch (a.n_det) {                                                                           \
-      case 1: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 1>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
-      case 2: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 2>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
-      case 3: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 3>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
-      case 4: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 4>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
-      default: hipLaunchKernelGGL((k_pass1<double, PlanD##id, 0>), dim3(grid), dim3(PlanD##id::T1), 0, s, a); break; \
+      case 1: launch_k(k_pass1<double, PlanD##id, 1>, dim3(grid), dim3(PlanD##id::T1), s, e0, e1, a); break; \
+      case 2: launch_k(k_pass1<double, PlanD##id, 2>, dim3(grid), dim3(PlanD##id::T1), s, e0, e1, a); break; \
+      case 3: launch_k(k_pass1<double, PlanD##id, 3>, dim3(grid), dim3(PlanD##id::T1), s, e0, e1, a); break; \
+      case 4: launch_k(k_pass1<double, PlanD##id, 4>, dim3(grid), dim3(PlanD##id::T1), s, e0, e1, a); break; \
+      default: launch_k(k_pass1<double, PlanD##id, 0>, dim3(grid), dim3(PlanD##id::T1), s, e0, e1, a); break; \
     }                                                                                            \
     break;
 #define FCAS_CASE_P2(id, ...)                                                              \
   case id:                                                                                  \
-    hipLaunchKernelGGL((k_pass2<double, PlanD##id>), dim3(grid), dim3(PlanD##id::T2), 0, s, a); \
+    launch_k(k_pass2<double, PlanD##id>, dim3(grid), dim3(PlanD##id::T2), s, e0, e1, a); \
     break;
 
-hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
+hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_CASE_P1)
     default:
@@ -29,9 +29,9 @@ hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s
 
 #define FCAS_CASE_PM(id, ...) \
   case id:                    \
-    return launch_passm_plan<double, PlanD##id>(a, grid, s);
+    return launch_passm_plan<double, PlanD##id>(a, grid, s, e0, e1);
 
-hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
+hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_CASE_PM)
     default:
@@ -39,7 +39,7 @@ hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s
   }
 }
 
-hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s) {
+hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (plan) {
     FCAS_PLAN_LIST(FCAS_CASE_P2)
     default:

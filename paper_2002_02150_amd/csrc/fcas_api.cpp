@@ -472,19 +472,17 @@ namespace {
 
 hipError_t timed_launch(fcas_ctx* ctx, std::vector<TimedPair>& rec, hipStream_t s, int pass, int plan,
                         const PassArgs& a, int grid) {
+  // with timing on, the launch itself records the two events at the kernel's
+  // start and end (hipExtLaunchKernel)
   TimedPair tp{};
   if (ctx->timing) {
     hipEventCreate(&tp.a);
     hipEventCreate(&tp.b);
-    hipEventRecord(tp.a, s);
   }
-  hipError_t e = pass == 1   ? launch_pass1(ctx->prec, plan, a, grid, s)
-                 : pass == 3 ? launch_passm(ctx->prec, plan, a, grid, s)
-                             : launch_pass2(ctx->prec, plan, a, grid, s);
-  if (ctx->timing) {
-    hipEventRecord(tp.b, s);
-    rec.push_back(tp);
-  }
+  hipError_t e = pass == 1   ? launch_pass1(ctx->prec, plan, a, grid, s, tp.a, tp.b)
+                 : pass == 3 ? launch_passm(ctx->prec, plan, a, grid, s, tp.a, tp.b)
+                             : launch_pass2(ctx->prec, plan, a, grid, s, tp.a, tp.b);
+  if (ctx->timing) rec.push_back(tp);
   return e;
 }
 
@@ -833,25 +831,28 @@ int fcas_read_timing(fcas_ctx* ctx, const char* which, double* total_ms, int64_t
 
 // precision dispatch of the pass launchers (the instantiations live in eval_f32.hip / eval_f64.hip)
 namespace fcas {
-hipError_t launch_pass1_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_passm_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s);
+hipError_t launch_pass1_f32(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_pass1_f64(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_passm_f32(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_passm_f64(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_pass2_f32(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+hipError_t launch_pass2_f64(int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 hipError_t launch_finalize_f32(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, int, const int32_t*,
                                int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 hipError_t launch_finalize_f64(const EvalDesc*, const SegDesc*, const void*, const int32_t*, int, int, const int32_t*,
                                int32_t*, unsigned long long*, double*, int32_t*, hipStream_t);
 
-hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
-  return precision ? launch_pass1_f64(plan, a, grid, s) : launch_pass1_f32(plan, a, grid, s);
+hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
+  return precision ? launch_pass1_f64(plan, a, grid, s, e0, e1) : launch_pass1_f32(plan, a, grid, s, e0, e1);
 }
-hipError_t launch_passm(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
-  return precision ? launch_passm_f64(plan, a, grid, s) : launch_passm_f32(plan, a, grid, s);
+hipError_t launch_passm(int precision, int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
+  return precision ? launch_passm_f64(plan, a, grid, s, e0, e1) : launch_passm_f32(plan, a, grid, s, e0, e1);
 }
-hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s) {
-  return precision ? launch_pass2_f64(plan, a, grid, s) : launch_pass2_f32(plan, a, grid, s);
+hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
+  return precision ? launch_pass2_f64(plan, a, grid, s, e0, e1) : launch_pass2_f32(plan, a, grid, s, e0, e1);
 }
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
                            const int32_t* part_j, int n, int part_stride, const int32_t* plan_parts2,

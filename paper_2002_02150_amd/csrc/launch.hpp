@@ -3,11 +3,24 @@
 // given stream and returns the hipError_t of the launch.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "eval_kernels.hpp"
 
 namespace fcas {
+
+// A pass-kernel launch; with timing events (e0, e1 not null) the events are
+// recorded by the kernel's own dispatch (hipExtLaunchKernel), so that they
+// bracket the kernel and not the event packets around it.  Capturable code
+// passes no events and takes the plain launch.
+template <typename K, typename... A>
+inline void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0, hipEvent_t e1, A... args) {
+  if (e0 || e1)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
+}
 
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
 hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* theta, const int32_t* seg_ids,
@@ -18,10 +31,13 @@ hipError_t launch_setup(const NetDesc* net, const SegDesc* segs, const double* t
 hipError_t launch_fused_f32(int plan, const FusedArgs& f, int grid, hipStream_t s);
 int fused_blocks_per_cu(int plan);
 
-// precision: 0 float, 1 double
-hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
-hipError_t launch_passm(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);   // three-pass plans
-hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s);
+// precision: 0 float, 1 double; e0 / e1: optional timing events (launch_k)
+hipError_t launch_pass1(int precision, int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
+hipError_t launch_passm(int precision, int plan, const PassArgs& a, int grid, hipStream_t s,   // three-pass plans
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+hipError_t launch_pass2(int precision, int plan, const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 hipError_t launch_finalize(int precision, const EvalDesc* evals, const SegDesc* segs, const void* part_g,
                            const int32_t* part_j, int n, int part_stride, const int32_t* plan_parts2,
                            int32_t* counts, unsigned long long* evaluated, double* fitness, int32_t* argmax,
@@ -35,9 +51,9 @@ template <class PL>
 constexpr bool kFusable = !PL::THREE && PL::T1 == PL::T2;
 
 template <typename Real, class PL>
-hipError_t launch_passm_plan(const PassArgs& a, int grid, hipStream_t s) {
+hipError_t launch_passm_plan(const PassArgs& a, int grid, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if constexpr (PL::THREE) {
-    hipLaunchKernelGGL((k_passm<Real, PL>), dim3(grid), dim3(PL::TM), 0, s, a);
+    launch_k(k_passm<Real, PL>, dim3(grid), dim3(PL::TM), s, e0, e1, a);
     return hipGetLastError();
   } else {
     return hipErrorInvalidValue;
