@@ -71,6 +71,26 @@ def search(ctx, n_seg, cfg: PsoConfig, group=20):
     return sw
 
 
+def bootstrap_metric(records, n_runs, n_iter, n_boot=2000, seed=0, quantiles=(0.01, 0.99)):
+    """Bootstrap distribution of M(N_runs, N_iter) (Sec. V.A, reading A21):
+    each resample draws the realizations with replacement and, for each drawn
+    realization, N_runs of its recorded run bests with replacement; the
+    resample's M is the fraction whose best of those runs is below rho0^2.
+    Returns the requested quantiles of the n_boot resampled values and their
+    mean."""
+    rng = np.random.default_rng(seed)
+    rb = np.array([r["run_best"][str(n_iter)] for r in records], dtype=np.float64)      # [R][runs]
+    r0 = np.array([r["rho0_sq"] for r in records], dtype=np.float64)
+    R, runs = rb.shape
+    vals = np.empty(n_boot)
+    for b in range(n_boot):
+        pick = rng.integers(0, R, R)
+        draw = rng.integers(0, runs, (R, n_runs))
+        best = rb[pick[:, None], draw].max(axis=1)
+        vals[b] = np.mean(best < r0[pick])
+    return [float(np.quantile(vals, q)) for q in quantiles], float(vals.mean())
+
+
 def _injection(source, r, snr, rng):
     import synth
     if source == "random":
@@ -86,7 +106,8 @@ def _injection(source, r, snr, rng):
 def run(realizations=120, snr=9.0, n_iters=(500, 1000, 1500), n_runs_list=(2, 4, 6, 8, 10, 12), source="L4",
         batch=8, seed=2002, keep_data=False, log=print):
     """Returns the table M(N_runs, N_iter) and per-realization records:
-    rho0_sq, theta0 and, for every "N_runs x N_iter", the best-of-runs rho'^2
+    rho0_sq, theta0, the best fitness of each of the 12 runs per N_iter
+    (run_best) and, for every "N_runs x N_iter", the best-of-runs rho'^2
     with its theta and sample.  keep_data: also the host copy of each
     realization's Fourier data (the PSD is synth.psd_matrix)."""
     import synth
@@ -126,6 +147,9 @@ def run(realizations=120, snr=9.0, n_iters=(500, 1000, 1500), n_runs_list=(2, 4,
             cfg = PsoConfig(n_runs=len(rs) * MAX_RUNS, n_particles=PARTICLES, n_iter=it,
                             seed=seed * 1000003 + 7919 * sidx + 101 * b0 + it)
             sw = search(ctx, len(rs), cfg)
+            rb = sw.best_f.view(len(rs), MAX_RUNS).cpu().numpy()
+            for k, rec in enumerate(recs):
+                rec.setdefault("run_best", {})[str(it)] = rb[k].tolist()
             for m in n_runs_list:
                 f, th, j, _ = (t.cpu().numpy() for t in sw.best_segments(MAX_RUNS, m))
                 for k, rec in enumerate(recs):
@@ -157,6 +181,9 @@ def main(argv=None):
               tuple(int(x) for x in a.runs.split(",")), a.source, a.batch, log=lambda s: print(s, flush=True))
     summary = {k: v for k, v in out.items() if k != "records"}
     summary["rho0_sq_median"] = float(np.median([r["rho0_sq"] for r in out["records"]]))
+    summary["bootstrap_p01_p99"] = {f"{m}x{it}": bootstrap_metric(out["records"], m, it)[0]
+                                    for m in out["n_runs"] for it in out["n_iters"]}
+    summary["run_best"] = [dict(rho0_sq=r["rho0_sq"], run_best=r["run_best"]) for r in out["records"]]
     print(json.dumps(summary))
     return 0
 

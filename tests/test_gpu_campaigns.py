@@ -53,6 +53,9 @@ def test_tuning_metric_small_matches_oracle():
             _check(rec["xf"], net, b["theta"], b["rho_sq"], b["argmax"])
         for it in (20, 30):
             assert rec["best"][f"4x{it}"]["rho_sq"] >= rec["best"][f"2x{it}"]["rho_sq"]
+            # the recorded run bests (used by the bootstrap) give the same best of the first m runs
+            for m in (2, 4):
+                assert max(rec["run_best"][str(it)][:m]) == rec["best"][f"{m}x{it}"]["rho_sq"]
     for key, v in out["table"].items():
         assert v == np.mean([r["best"][key]["rho_sq"] < r["rho0_sq"] for r in out["records"]])
 

@@ -127,3 +127,21 @@ def test_hour_h0_combine_checks():
         combine([a, a])
     with pytest.raises(ValueError):
         combine([a, dict(b, f_low=30.0)])
+
+
+def test_tuning_metric_bootstrap():
+    """The bootstrap of M(N_runs, N_iter) (Sec. V.A): all runs above the truth
+    give 0, all below give 1; with one realization whose two runs straddle the
+    truth, a draw of N_runs runs with replacement ends below it with
+    probability 2^-N_runs, which the bootstrap mean reproduces."""
+    from paper_2002_02150_amd.tuning_metric import bootstrap_metric
+    above = [dict(rho0_sq=100.0, run_best={"500": [101.0, 120.0, 100.5]}) for _ in range(5)]
+    below = [dict(rho0_sq=100.0, run_best={"500": [90.0, 99.0, 80.0]}) for _ in range(5)]
+    assert bootstrap_metric(above, 2, 500, n_boot=200) == ([0.0, 0.0], 0.0)
+    assert bootstrap_metric(below, 2, 500, n_boot=200) == ([1.0, 1.0], 1.0)
+    mixed = [dict(rho0_sq=100.0, run_best={"500": [90.0, 110.0]})]
+    for m in (1, 2, 3):
+        _, mean = bootstrap_metric(mixed, m, 500, n_boot=20000, seed=m)
+        assert mean == pytest.approx(0.5 ** m, abs=0.015)
+    (p1, p99), _ = bootstrap_metric(above[:3] + below[:2], 1, 500, n_boot=4000)
+    assert 0.0 <= p1 < 0.4 < p99 <= 1.0
