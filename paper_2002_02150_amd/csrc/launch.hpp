@@ -101,7 +101,7 @@ struct TailArgs {
   unsigned long long* evaluated;
   double* fitness;
   int32_t* argmax;
-  double* theta;                 // written by the update (next points), then read by the set-up
+  double* theta;                 // the next points, written by the update (the set-up reads its LDS copy)
   const int32_t* seg_ids;
   int32_t* err;
   int32_t setup;                 // 0: last iteration, no set-up
