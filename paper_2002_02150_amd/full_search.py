@@ -7,10 +7,10 @@ covers).
 
 Data: a seeded Gaussian time series per detector (H, L, V, K) at 2048 Hz with
 the analytic PSD above 20 Hz, cut into overlapping 128-s segments (262144
-samples) at a common stride; 8 double-neutron-star injections (component
-masses U[1.2, 1.6] Msun, isotropic sky and orientation, network SNR U[10, 12],
-coalescence uniform over the hour from 128 s on, so that every chirp starts
-inside the data).  Each injection is synthesised once over the whole stretch
+samples) at a common stride, the last one ending with the data; 8
+double-neutron-star injections (component masses U[1.2, 1.6] Msun, isotropic
+sky and orientation, network SNR U[10, 12], coalescence uniform over the hour
+from 128 s on, so that every chirp starts inside the data).  Each injection is synthesised once over the whole stretch
 (fcas_inject on the Fourier grid of the full length, network SNR over the
 stretch), brought to the time domain and added to the noise series before the
 segments are cut, so that every segment overlapping a chirp holds the part of
@@ -53,15 +53,25 @@ RUNS, PARTICLES = 8, 40
 
 
 def layout(total: int, n_seg: int, seg: int = SEG):
-    """Segment starts (common stride) and the searched coalescence range of each."""
+    """Segment starts and the searched coalescence range of each.  The segments
+    follow a common stride, except the last, which starts where it ends with
+    the data (up to n_seg - 2 samples later than the stride puts it); every
+    range continues where the previous one ends, so the ranges tile
+    [0, total) with no gap or overlap."""
+    if n_seg < 2 or total < seg:
+        raise ValueError(f"need at least two segments of {seg} samples, got {n_seg} over {total}")
     stride = (total - seg) // (n_seg - 1)
-    starts = [k * stride for k in range(n_seg)]
+    if stride > seg:
+        raise ValueError(f"{n_seg} segments of {seg} samples leave gaps in {total} samples")
+    starts = [k * stride for k in range(n_seg - 1)] + [total - seg]
     margin = (seg - stride) // 2
     ranges = []
+    end = 0                              # where the previous range ends (absolute sample)
     for k in range(n_seg):
-        lo = 0 if k == 0 else margin
+        lo = end - starts[k]
         hi = seg if k == n_seg - 1 else margin + stride
         ranges.append((lo, hi))
+        end = starts[k] + hi
     return starts, stride, ranges
 
 

@@ -145,3 +145,25 @@ def test_tuning_metric_bootstrap():
         assert mean == pytest.approx(0.5 ** m, abs=0.015)
     (p1, p99), _ = bootstrap_metric(above[:3] + below[:2], 1, 500, n_boot=4000)
     assert 0.0 <= p1 < 0.4 < p99 <= 1.0
+
+
+def test_full_search_layout_tiles_the_data():
+    """The overlapping segments of the full-length search cover the data up to
+    its last sample, and their searched coalescence ranges tile [0, total)
+    with no gap or overlap, for the hour's 56 segments and other counts."""
+    from paper_2002_02150_amd.full_search import SEG, layout
+    for total, n in ((7372800, 56), (491520, 3), (2 * SEG, 2), (1000003, 7), (SEG + 5, 2)):
+        starts, stride, ranges = layout(total, n)
+        assert len(starts) == len(ranges) == n
+        assert starts[0] == 0 and starts[-1] + SEG == total
+        assert all(0 < b - a <= stride + n - 2 for a, b in zip(starts, starts[1:]))
+        end = 0
+        for s, (lo, hi) in zip(starts, ranges):
+            assert 0 <= lo < hi <= SEG
+            assert s + lo == end
+            end = s + hi
+        assert end == total
+    with pytest.raises(ValueError):
+        layout(10 * SEG, 3)          # windows too far apart to overlap
+    with pytest.raises(ValueError):
+        layout(SEG - 1, 2)
